@@ -1,0 +1,234 @@
+"""Seeded synthetic workloads for the ORCA step.
+
+This module only draws inputs: start positions, goals, preferred velocities for
+the fixed-leaf workload, and the per-scene parameters.  It contains none of the
+collision-avoidance arithmetic, so both the GPU library and the CPU reference can
+consume its output without sharing any of the method's code.
+
+The paper (section 4) evaluates on synthetic crossing scenarios whose people
+spawn at random non-overlapping points; it names no public dataset.  The five
+workloads below follow that recipe at the sizes the measurements use:
+
+* ``uniform_rsa``   1,024 agents at 0.5 agents/m^2, random sequential addition
+  with minimum separation 2r, goals uniform in the same square.
+* ``ring``          65,536 agents evenly spaced on a 1,200 m circle, goal = the
+  antipodal point.
+* ``dense_uniform`` 1,048,576 agents uniform at 2 agents/m^2 (no rejection, so
+  many pairs start overlapping and many LPs are infeasible), K=16, 3 m radius.
+* ``batched``       512 independent scenes with log-uniform sizes in [64, 16384],
+  per-scene density, max speed and time horizon.
+* ``grad``          4,096 agents uniform at 1 agent/m^2 with a fixed preferred
+  velocity per agent and a target point per agent.
+
+Every generator is deterministic in its seed (``numpy.random.default_rng``).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+BASE_SEED = 190810107
+
+# Agent parameters shared by the single-scene workloads.
+DEFAULT_PARAMS = dict(radius=0.25, max_speed=1.5, neighbor_dist=5.0,
+                      time_horizon=5.0, dt=0.1, pref_speed=1.3, max_neighbors=10)
+
+
+@dataclasses.dataclass
+class SceneParams:
+    radius: float = 0.25
+    max_speed: float = 1.5
+    neighbor_dist: float = 5.0
+    time_horizon: float = 5.0
+    dt: float = 0.1
+    pref_speed: float = 1.3
+    max_neighbors: int = 10
+
+
+@dataclasses.dataclass
+class Workload:
+    """A batch of independent scenes laid out back to back.
+
+    Arrays are float32 ``[2, N]`` (row 0 = x, row 1 = y) over all agents of all
+    scenes; scene ``s`` owns agents ``offsets[s]:offsets[s+1]``.
+    """
+    name: str
+    pos: np.ndarray
+    vel: np.ndarray
+    goals: Optional[np.ndarray]
+    pref_vel: np.ndarray
+    offsets: np.ndarray
+    params: List[SceneParams]
+    steps: int
+    targets: Optional[np.ndarray] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def n_scenes(self) -> int:
+        return len(self.params)
+
+    def subset_scenes(self, idx) -> "Workload":
+        """Return a workload made of the listed scenes only (copied)."""
+        idx = list(idx)
+        parts = [(int(self.offsets[s]), int(self.offsets[s + 1])) for s in idx]
+        cat = lambda a: None if a is None else np.ascontiguousarray(
+            np.concatenate([a[:, lo:hi] for lo, hi in parts], axis=1))
+        sizes = [hi - lo for lo, hi in parts]
+        offs = np.zeros(len(idx) + 1, np.int64)
+        offs[1:] = np.cumsum(sizes)
+        return Workload(self.name + "_subset", cat(self.pos), cat(self.vel), cat(self.goals),
+                        cat(self.pref_vel), offs, [self.params[s] for s in idx], self.steps,
+                        cat(self.targets))
+
+
+def _rsa_square(rng: np.random.Generator, n: int, side: float, dmin: float,
+                margin: float = 1e-4) -> np.ndarray:
+    """Random sequential addition of ``n`` points in ``[-side/2, side/2]^2``.
+
+    Proposals are drawn in batches; a proposal is kept if it is at least
+    ``dmin + margin`` from every kept point and from every earlier proposal
+    of its batch.  The margin keeps the separation >= ``dmin`` after the
+    coordinates are rounded to float32.
+    """
+    from scipy.spatial import cKDTree
+
+    need = dmin + margin
+    kept = np.empty((0, 2))
+    tries = 0
+    while kept.shape[0] < n:
+        tries += 1
+        if tries > 10000:
+            raise RuntimeError("random sequential addition did not converge")
+        b = max(2 * (n - kept.shape[0]), 256)
+        cand = (rng.random((b, 2)) - 0.5) * side
+        if kept.shape[0]:
+            d, _ = cKDTree(kept).query(cand, k=1)
+            cand = cand[d >= need]
+        if cand.shape[0] > 1:
+            pairs = cKDTree(cand).query_pairs(need, output_type="ndarray")
+            if pairs.size:
+                drop = np.zeros(cand.shape[0], bool)
+                drop[pairs.max(axis=1)] = True
+                cand = cand[~drop]
+        kept = np.concatenate([kept, cand[: n - kept.shape[0]]], axis=0)
+    return kept
+
+
+def _check_separation(p32: np.ndarray, dmin: float) -> None:
+    from scipy.spatial import cKDTree
+    pts = p32.T.astype(np.float64)
+    if pts.shape[0] > 1:
+        d, _ = cKDTree(pts).query(pts, k=2)
+        assert d[:, 1].min() >= dmin, "separation lost in float32 rounding"
+
+
+def _pack(name, pos_list, goal_list, params, steps, pref_list=None, targets=None):
+    pos = np.ascontiguousarray(np.concatenate(pos_list, axis=1).astype(np.float32))
+    goals = None if goal_list is None else np.ascontiguousarray(
+        np.concatenate(goal_list, axis=1).astype(np.float32))
+    n = pos.shape[1]
+    pref = (np.zeros((2, n), np.float32) if pref_list is None else
+            np.ascontiguousarray(np.concatenate(pref_list, axis=1).astype(np.float32)))
+    offs = np.zeros(len(pos_list) + 1, np.int64)
+    offs[1:] = np.cumsum([p.shape[1] for p in pos_list])
+    return Workload(name, pos, np.zeros((2, n), np.float32), goals, pref, offs, params, steps,
+                    targets)
+
+
+def uniform_rsa(n: int = 1024, density: float = 0.5, seed: int = BASE_SEED + 0,
+                steps: int = 100, **over) -> Workload:
+    """Uniform square, rejection-sampled to separation 2r; goals uniform."""
+    rng = np.random.default_rng(seed)
+    p = SceneParams(**{**DEFAULT_PARAMS, **over})
+    side = math.sqrt(n / density)
+    pos = _rsa_square(rng, n, side, 2 * p.radius).T.astype(np.float32)
+    _check_separation(pos, 2 * p.radius)
+    goals = ((rng.random((n, 2)) - 0.5) * side).T
+    return _pack("uniform_rsa", [pos], [goals], [p], steps)
+
+
+def ring(n: int = 65536, radius_m: float = 1200.0, steps: int = 2000, **over) -> Workload:
+    """Agents evenly spaced on a circle; each heads for the antipodal point."""
+    p = SceneParams(**{**DEFAULT_PARAMS, **over})
+    th = 2.0 * np.pi * np.arange(n, dtype=np.float64) / n
+    pos = np.stack([radius_m * np.cos(th), radius_m * np.sin(th)])
+    return _pack("ring", [pos], [-pos], [p], steps)
+
+
+def dense_uniform(n: int = 1 << 20, density: float = 2.0, seed: int = BASE_SEED + 2,
+                  steps: int = 500, **over) -> Workload:
+    """Plain uniform square (no rejection): overlapping starts, many infeasible LPs."""
+    rng = np.random.default_rng(seed)
+    kw = {**DEFAULT_PARAMS, "max_neighbors": 16, "neighbor_dist": 3.0}
+    kw.update(over)
+    p = SceneParams(**kw)
+    side = math.sqrt(n / density)
+    pos = ((rng.random((n, 2)) - 0.5) * side).T
+    goals = ((rng.random((n, 2)) - 0.5) * side).T
+    return _pack("dense_uniform", [pos], [goals], [p], steps)
+
+
+def batched(n_scenes: int = 512, seed: int = BASE_SEED + 3, steps: int = 300,
+            n_min: int = 64, n_max: int = 16384) -> Workload:
+    """Independent scenes of log-uniform size with per-scene density, v_max and tau."""
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(np.exp(rng.uniform(math.log(n_min), math.log(n_max), n_scenes))).astype(int)
+    dens = rng.uniform(0.3, 2.0, n_scenes)
+    vmax = rng.uniform(1.0, 2.0, n_scenes)
+    tau = rng.uniform(2.0, 8.0, n_scenes)
+    pos_l, goal_l, params = [], [], []
+    for s in range(n_scenes):
+        p = SceneParams(**{**DEFAULT_PARAMS, "max_speed": float(vmax[s]),
+                           "time_horizon": float(tau[s])})
+        side = math.sqrt(sizes[s] / dens[s])
+        pos = _rsa_square(rng, int(sizes[s]), side, 2 * p.radius).T.astype(np.float32)
+        _check_separation(pos, 2 * p.radius)
+        pos_l.append(pos)
+        goal_l.append(((rng.random((int(sizes[s]), 2)) - 0.5) * side).T)
+        params.append(p)
+    return _pack("batched", pos_l, goal_l, params, steps)
+
+
+def grad(n: int = 4096, density: float = 1.0, seed: int = BASE_SEED + 4, steps: int = 200,
+         **over) -> Workload:
+    """Uniform square with a fixed preferred velocity per agent and a target per agent.
+
+    The preferred velocity has speed ``pref_speed`` and a uniform random heading;
+    targets come from a separate random stream.
+    """
+    rng = np.random.default_rng(seed)
+    p = SceneParams(**{**DEFAULT_PARAMS, **over})
+    side = math.sqrt(n / density)
+    pos = ((rng.random((n, 2)) - 0.5) * side).T
+    ang = rng.uniform(0.0, 2.0 * np.pi, n)
+    pref = p.pref_speed * np.stack([np.cos(ang), np.sin(ang)])
+    trng = np.random.default_rng(seed + 1000)
+    targets = ((trng.random((n, 2)) - 0.5) * side).T.astype(np.float32)
+    return _pack("grad", [pos], None, [p], steps, pref_list=[pref], targets=targets)
+
+
+def tiny_random(n: int, side: float, seed: int, vel_scale: float = 1.0, **over) -> Workload:
+    """Small uniform scene with random current and preferred velocities (parity cases)."""
+    rng = np.random.default_rng(seed)
+    p = SceneParams(**{**DEFAULT_PARAMS, **over})
+    pos = ((rng.random((n, 2)) - 0.5) * side).T
+    w = _pack("tiny_random", [pos], [((rng.random((n, 2)) - 0.5) * side).T], [p], 1,
+              pref_list=[(rng.random((n, 2)) - 0.5).T * 2.0 * p.pref_speed])
+    w.vel = np.ascontiguousarray(((rng.random((n, 2)) - 0.5).T * 2.0 * vel_scale)
+                                 .astype(np.float32))
+    return w
+
+
+WORKLOADS = {
+    "uniform_rsa": uniform_rsa,
+    "ring": ring,
+    "dense_uniform": dense_uniform,
+    "batched": batched,
+    "grad": grad,
+}
