@@ -1,0 +1,192 @@
+/*
+ * orca.h -- C ABI of the MI355X (gfx950) ORCA crowd step.
+ *
+ * One timestep of optimal reciprocal collision avoidance as described in
+ * Charlton et al., "Fast Simulation of Crowd Collision Avoidance":
+ *   - agents are binned into a uniform grid of square cells at least as wide
+ *     as the observation radius (section 3, Fig. 2: messages sorted into
+ *     spatial bins, each agent reading its own and the neighbouring bins);
+ *   - each agent keeps the K nearest others closer than the observation
+ *     radius (Fig. 2's radius filter; the cap K is the memory remedy of
+ *     section 5);
+ *   - each kept neighbour contributes one half-plane of permitted velocities
+ *     (Fig. 1(b)-(c)): the velocity obstacle for look-ahead tau, the shortest
+ *     vector u from the relative velocity to its boundary, and the half-plane
+ *     through v + u/2 whose normal points along u -- each agent takes half of
+ *     the avoidance (section 2 on reciprocal velocity obstacles);
+ *   - a linear program picks the permitted velocity closest to the preferred
+ *     one inside the max-speed disc (section 3); if no velocity is permitted
+ *     it picks the one that least penetrates the half-planes (section 3),
+ *     then, within 1e-5 m/s of that least penetration, the one closest to the
+ *     preferred velocity;
+ *   - every agent is updated from the same state, then x += dt v'.
+ *   Pairs already closer than their combined radius use dt in place of tau
+ *   (they must separate within one step).  Exact head-on pairs dodge to
+ *   their own right; coincident pairs split along x by agent index.
+ *
+ * Memory and layout
+ *   - Every state array is a caller-owned DEVICE pointer to float32 in
+ *     structure-of-arrays form [2, N]: element i holds x_i (or vx_i), element
+ *     N + i holds y_i (or vy_i).  The library never frees caller memory.
+ *   - Scenes: n_scenes independent crowds stored back to back; scene s owns
+ *     agents scene_offsets[s] .. scene_offsets[s+1]-1 (host array, n_scenes+1
+ *     entries, first entry 0, non-decreasing, last entry N).  Agents of
+ *     different scenes never see each other.  Neighbour ids are global
+ *     agent indices.
+ *   - The context owns all scratch memory: it is allocated once by
+ *     orca_create, so orca_build_grid, orca_compute_velocities and orca_step
+ *     allocate nothing.
+ *   - Every call only enqueues work on the context's HIP stream and returns;
+ *     outputs are ready when that stream reaches them.
+ *
+ * Errors
+ *   Every call returns ORCA_OK (0) or a negative code; orca_last_error gives a
+ *   message.  Arguments are validated on the host before anything is
+ *   enqueued.  NaN or infinite values in device data are not checked: the
+ *   results are then unspecified, but every access stays in bounds.
+ *
+ * Precision
+ *   State is float32.  Neighbour distances are compared in float32 (squared
+ *   distance, each operation rounded separately); half-planes and linear
+ *   programs are solved in float64 and the results rounded to float32.
+ *   Outputs are bitwise reproducible run to run.
+ */
+#ifndef ORCA_H
+#define ORCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    ORCA_OK = 0,
+    ORCA_EINVAL = -1,    /* bad argument (null pointer, non-finite or out-of-range value) */
+    ORCA_ENOMEM = -2,    /* device allocation failed in orca_create */
+    ORCA_ECAPACITY = -3, /* more agents, scenes or neighbours than the context was made for */
+    ORCA_ESTATE = -4,    /* call order: velocities without a grid of the same positions */
+    ORCA_EHIP = -5       /* a HIP runtime call or kernel launch failed */
+};
+
+/* Largest neighbour cap a context accepts. */
+#define ORCA_K_LIMIT 32
+
+typedef struct orca_ctx orca_ctx;
+
+/* Per-scene parameters (host memory).  All agents of a scene share them. */
+typedef struct orca_params {
+    float radius;          /* agent radius r (m), >= 0; a pair's combined radius is 2r */
+    float max_speed;       /* v_max (m/s), > 0: the velocity disc */
+    float neighbor_dist;   /* observation radius (m), > 0; neighbours are strictly closer */
+    float time_horizon;    /* look-ahead tau (s), > 0 */
+    float dt;              /* time step (s), > 0 */
+    float pref_speed;      /* walking speed for goal steering (m/s), >= 0 */
+    int32_t max_neighbors; /* K, 0 .. the context's k_max */
+    int32_t reserved;      /* must be 0 */
+} orca_params;
+
+/*
+ * Create a context for up to max_agents agents in up to max_scenes scenes
+ * with neighbour caps up to k_max (1 .. ORCA_K_LIMIT).  tape_steps reserves
+ * room for that many recorded steps for orca_backward (0 = no tape).
+ * hip_stream is a hipStream_t (NULL = the null stream) on the current device.
+ * On success *out owns all device scratch; release it with orca_destroy.
+ * Errors: EINVAL (out == NULL, sizes out of range), ECAPACITY (k_max above
+ * ORCA_K_LIMIT), ENOMEM, EHIP.  On error *out is NULL.
+ */
+int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t k_max,
+                int32_t tape_steps, void *hip_stream);
+
+/* Release a context (waits for its stream first).  NULL is ignored. */
+void orca_destroy(orca_ctx *ctx);
+
+/* Message of the last failed call on ctx (static text if ctx is NULL). */
+const char *orca_last_error(const orca_ctx *ctx);
+
+/* Make later calls enqueue on another stream of the same device. */
+int orca_set_stream(orca_ctx *ctx, void *hip_stream);
+
+/*
+ * Bin the agents (section 3, Fig. 2).  pos: device [2, N] with
+ * N = scene_offsets[n_scenes].  Per scene: bounding box, cells of side
+ * neighbor_dist * (1 + 2^-10) (wider if the context's cell budget would be
+ * exceeded), cell keys, a counting sort of the agents into cell order.
+ * The grid stays valid for orca_compute_velocities on the same pos pointer
+ * until orca_step or another orca_build_grid.
+ * Errors: EINVAL, ECAPACITY (N > max_agents, n_scenes > max_scenes,
+ * max_neighbors > k_max), EHIP.
+ */
+int orca_build_grid(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
+                    const orca_params *params, const float *pos);
+
+/*
+ * New velocities from one state, without moving anyone (sections 3 and 5).
+ * pos must be the pointer given to the last orca_build_grid (else ESTATE).
+ * vel: current velocities [2, N].  Preferred velocities: if goals (device
+ * [2, N]) is non-NULL each agent's preferred velocity points at its goal at
+ * pref_speed (or covers the remaining offset in one dt when closer than
+ * pref_speed * dt), else pref_vel [2, N] is used as given.
+ * Outputs (original agent order):
+ *   new_vel   [2, N] float32, required;
+ *   nbr_out   [N, K_s] int32 per scene block (row i has K of agent i's scene
+ *             entries: neighbour ids nearest first, ties by id, padded with
+ *             -1); the rows are packed with stride k_row = max over scenes of
+ *             max_neighbors; NULL to skip;
+ *   lp_status [N] uint8: 0 = the 2D program was feasible, 1 = least
+ *             penetration fallback; NULL to skip.
+ */
+int orca_compute_velocities(orca_ctx *ctx, const float *pos, const float *vel,
+                            const float *pref_vel, const float *goals, float *new_vel,
+                            int32_t *nbr_out, uint8_t *lp_status);
+
+/*
+ * Advance n_steps (>= 1) synchronous steps in place.  Each step bins the
+ * agents, picks every new velocity v' from the same state, then sets
+ * x <- x + dt v' and v <- v' (float32 results of float64 sums).  With goals
+ * (device [2, N], nullable) the preferred velocity is re-aimed at the goal at
+ * the start of every step and written to pref_vel; without, pref_vel is read
+ * only.  save_tape = 1 records the steps for orca_backward (needs tape_steps
+ * >= n_steps at create); 0 records nothing.
+ */
+int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
+              const orca_params *params, float *pos, float *vel, float *pref_vel,
+              const float *goals, int32_t n_steps, int32_t save_tape);
+
+/*
+ * Vector-Jacobian product of recorded step tape_step (0-based, of the last
+ * orca_step call with save_tape = 1; no goals).  Given the gradients of a loss
+ * with respect to the state after the step (g_pos_next, g_vel_next, device
+ * [2, N]), write the gradients with respect to the state before it (g_pos,
+ * g_vel, device [2, N], overwritten) and ADD the gradients with respect to
+ * the fixed preferred velocities (g_pref_vel [2, N]), each scene's max_speed
+ * (g_max_speed [n_scenes]) and time_horizon (g_time_horizon [n_scenes]).
+ * The discrete choices of the forward step (neighbour sets, half-plane
+ * branches, active constraints) are held fixed.
+ * Errors: EINVAL, ESTATE (no such recorded step), EHIP.
+ */
+int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
+                  const float *g_vel_next, float *g_pos, float *g_vel, float *g_pref_vel,
+                  float *g_max_speed, float *g_time_horizon);
+
+/*
+ * Diagnostics: per-stage GPU time of every pass (orca_compute_velocities, or
+ * one step of orca_step) measured with HIP events recorded on the context
+ * stream between the stages.  While enabled, each pass waits for its stream
+ * at the end (so enable it only for measurement).  Stages:
+ *   0 binning (bounding box, keys, scan, scatter; 0 for orca_compute_velocities),
+ *   1 neighbour gather, 2 half-planes + 2D LP, 3 least-penetration fallback.
+ * orca_profile(ctx, 1) clears the sums and starts; orca_profile(ctx, 0) stops.
+ * orca_profile_read gives the summed milliseconds per stage (stage_ms
+ * [ORCA_PROF_STAGES]), the number of passes, and the total number of agents
+ * that took the fallback in them.
+ */
+#define ORCA_PROF_STAGES 4
+int orca_profile(orca_ctx *ctx, int32_t enable);
+int orca_profile_read(orca_ctx *ctx, double *stage_ms, int64_t *passes, int64_t *fallback_agents);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ORCA_H */

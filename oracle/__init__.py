@@ -55,6 +55,8 @@ def lib():
         if not os.path.exists(_LIB):
             build(force=False)
         L = ctypes.CDLL(_LIB)
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = ctypes.c_int
         L.oracle_dist2_f32.argtypes = [F32, F32, F32, F32]
         L.oracle_dist2_f32.restype = F32
         L.oracle_knn_brute.argtypes = [I64, P, I64, I64, I64, F32, I32, P, P]
@@ -95,6 +97,10 @@ def params_array(params):
 
 
 # ---------------------------------------------------------------- primitives
+
+def threads() -> int:
+    return lib().oracle_threads()
+
 
 def dist2_f32(xi, yi, xj, yj) -> float:
     return lib().oracle_dist2_f32(xi, yi, xj, yj)

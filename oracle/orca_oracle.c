@@ -40,6 +40,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_ARC 0
 #define ORC_LEFT 1
@@ -59,6 +62,16 @@ typedef struct {
 typedef struct {
     double qx, qy, nx, ny;
 } halfplane;
+
+/* Threads the parallel loops use. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* Neighbour selection                                                 */

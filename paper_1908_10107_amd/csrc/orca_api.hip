@@ -1,0 +1,451 @@
+// orca_api.hip -- host side of the C ABI declared in include/orca.h.
+//
+// Validation happens on the host before anything is enqueued, so bad
+// arguments never reach a kernel.  All device memory is allocated in
+// orca_create; the per-step calls only enqueue kernels on the context stream.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "orca.h"
+#include "orca_internal.h"
+
+using orca::Counters;
+using orca::GridDev;
+using orca::SceneDev;
+
+struct orca_ctx {
+    int64_t max_agents = 0;
+    int32_t max_scenes = 0, k_max = 0, tape_steps = 0;
+    hipStream_t stream = nullptr;
+    uint32_t max_cells = 0;
+    int32_t n_tiles = 0, fb_blocks = 0;
+
+    // device scratch
+    int32_t *off = nullptr;
+    SceneDev *sp = nullptr;
+    int32_t *agent_scene = nullptr;
+    uint32_t *bbox = nullptr;
+    GridDev *grid = nullptr;
+    Counters *counters = nullptr;
+    int32_t *key = nullptr, *rank = nullptr, *counts = nullptr, *cell_start = nullptr;
+    uint32_t *partial = nullptr;
+    float4 *sorted = nullptr;
+    int32_t *sid = nullptr, *skey = nullptr, *inv = nullptr;
+    int32_t *nbr = nullptr, *ncount = nullptr, *fb_list = nullptr;
+    std::vector<void *> allocs;
+
+    // scene set currently on the device
+    int32_t n_scenes = 0;
+    int64_t n = 0;
+    int32_t kmax_cur = 0;
+    std::vector<int64_t> h_off;
+    std::vector<orca_params> h_par;
+    std::vector<int32_t> h_off32;
+    std::vector<SceneDev> h_sp;
+    bool uploaded = false;
+
+    // grid state
+    bool grid_valid = false;
+    const float *grid_pos = nullptr;
+
+    // per-stage timing (diagnostics): events on the context stream between stages
+    bool profiling = false;
+    hipEvent_t ev[ORCA_PROF_STAGES + 1] = {};
+    double stage_ms[ORCA_PROF_STAGES] = {0};
+    int64_t prof_steps = 0, prof_fallback = 0;
+
+    char err[512] = {0};
+};
+
+namespace {
+
+int fail(orca_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(c->err, sizeof(c->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+int hip_fail(orca_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, ORCA_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_OK(call)                                             \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);   \
+    } while (0)
+
+bool finite_pos(float v) { return isfinite(v) && v > 0.0f; }
+bool finite_nonneg(float v) { return isfinite(v) && v >= 0.0f; }
+
+// Host-only checks of a scene set; no HIP call.
+int check_scenes(orca_ctx *ctx, int32_t n_scenes, const int64_t *off, const orca_params *par)
+{
+    if (n_scenes < 1) return fail(ctx, ORCA_EINVAL, "n_scenes must be >= 1 (got %d)", n_scenes);
+    if (n_scenes > ctx->max_scenes)
+        return fail(ctx, ORCA_ECAPACITY, "n_scenes %d exceeds the context's %d", n_scenes,
+                    ctx->max_scenes);
+    if (!off || !par) return fail(ctx, ORCA_EINVAL, "scene_offsets and params must be non-NULL");
+    if (off[0] != 0) return fail(ctx, ORCA_EINVAL, "scene_offsets[0] must be 0");
+    for (int32_t s = 0; s < n_scenes; ++s)
+        if (off[s + 1] < off[s])
+            return fail(ctx, ORCA_EINVAL, "scene_offsets must be non-decreasing (scene %d)", s);
+    if (off[n_scenes] > ctx->max_agents)
+        return fail(ctx, ORCA_ECAPACITY, "%lld agents exceed the context's %lld",
+                    (long long)off[n_scenes], (long long)ctx->max_agents);
+    for (int32_t s = 0; s < n_scenes; ++s) {
+        const orca_params &p = par[s];
+        if (!finite_nonneg(p.radius) || !finite_pos(p.max_speed) ||
+            !finite_pos(p.neighbor_dist) || !finite_pos(p.time_horizon) || !finite_pos(p.dt) ||
+            !finite_nonneg(p.pref_speed) || p.reserved != 0)
+            return fail(ctx, ORCA_EINVAL,
+                        "scene %d: radius, pref_speed must be finite and >= 0; max_speed, "
+                        "neighbor_dist, time_horizon, dt finite and > 0; reserved 0", s);
+        if (p.max_neighbors < 0)
+            return fail(ctx, ORCA_EINVAL, "scene %d: max_neighbors must be >= 0", s);
+        if (p.max_neighbors > ctx->k_max)
+            return fail(ctx, ORCA_ECAPACITY, "scene %d: max_neighbors %d exceeds k_max %d", s,
+                        p.max_neighbors, ctx->k_max);
+    }
+    return ORCA_OK;
+}
+
+bool same_scenes(const orca_ctx *ctx, int32_t n_scenes, const int64_t *off, const orca_params *par)
+{
+    if (!ctx->uploaded || ctx->n_scenes != n_scenes) return false;
+    if (memcmp(ctx->h_off.data(), off, sizeof(int64_t) * (size_t)(n_scenes + 1)) != 0) return false;
+    return memcmp(ctx->h_par.data(), par, sizeof(orca_params) * (size_t)n_scenes) == 0;
+}
+
+// Validate and, if the scene set changed, upload it and rebuild the agent->scene map.
+int use_scenes(orca_ctx *ctx, int32_t n_scenes, const int64_t *off, const orca_params *par)
+{
+    int rc = check_scenes(ctx, n_scenes, off, par);
+    if (rc != ORCA_OK) return rc;
+    if (same_scenes(ctx, n_scenes, off, par)) return ORCA_OK;
+    // the staging vectors may still feed an earlier copy: let the stream drain first
+    if (ctx->uploaded) HIP_OK(hipStreamSynchronize(ctx->stream));
+    ctx->n_scenes = n_scenes;
+    ctx->n = off[n_scenes];
+    ctx->h_off.assign(off, off + n_scenes + 1);
+    ctx->h_par.assign(par, par + n_scenes);
+    ctx->h_off32.resize((size_t)n_scenes + 1);
+    ctx->h_sp.resize((size_t)n_scenes);
+    ctx->kmax_cur = 0;
+    for (int32_t s = 0; s <= n_scenes; ++s) ctx->h_off32[s] = (int32_t)off[s];
+    for (int32_t s = 0; s < n_scenes; ++s) {
+        SceneDev d;
+        d.radius = par[s].radius;
+        d.vmax = par[s].max_speed;
+        d.nd = par[s].neighbor_dist;
+        d.tau = par[s].time_horizon;
+        d.dt = par[s].dt;
+        d.pref_speed = par[s].pref_speed;
+        volatile float nd = par[s].neighbor_dist;
+        d.nd2 = nd * nd;  // float32 product, as every distance test rounds it
+        d.k = par[s].max_neighbors;
+        ctx->h_sp[s] = d;
+        if (d.k > ctx->kmax_cur) ctx->kmax_cur = d.k;
+    }
+    HIP_OK(hipMemcpyAsync(ctx->off, ctx->h_off32.data(), sizeof(int32_t) * (size_t)(n_scenes + 1),
+                          hipMemcpyHostToDevice, ctx->stream));
+    HIP_OK(hipMemcpyAsync(ctx->sp, ctx->h_sp.data(), sizeof(SceneDev) * (size_t)n_scenes,
+                          hipMemcpyHostToDevice, ctx->stream));
+    HIP_OK(orca::launch_scene_map(ctx->off, n_scenes, ctx->agent_scene, (int32_t)ctx->n, ctx->bbox,
+                                  ctx->stream));
+    ctx->uploaded = true;
+    ctx->grid_valid = false;
+    return ORCA_OK;
+}
+
+orca::Plan make_plan(const orca_ctx *ctx)
+{
+    orca::Plan p{};
+    p.n = (int32_t)ctx->n;
+    p.n_scenes = ctx->n_scenes;
+    p.ld = (int32_t)ctx->max_agents;
+    p.fb_blocks = ctx->fb_blocks;
+    p.max_cells = ctx->max_cells;
+    p.off = ctx->off;
+    p.sp = ctx->sp;
+    p.agent_scene = ctx->agent_scene;
+    p.bbox = ctx->bbox;
+    p.grid = ctx->grid;
+    p.counters = ctx->counters;
+    p.key = ctx->key;
+    p.rank = ctx->rank;
+    p.counts = ctx->counts;
+    p.cell_start = ctx->cell_start;
+    p.partial = ctx->partial;
+    p.sorted = ctx->sorted;
+    p.sid = ctx->sid;
+    p.skey = ctx->skey;
+    p.inv = ctx->inv;
+    p.nbr = ctx->nbr;
+    p.ncount = ctx->ncount;
+    p.fb_list = ctx->fb_list;
+    return p;
+}
+
+#define STAGE_MARK(i)                                                        \
+    do {                                                                     \
+        if (ctx->profiling) HIP_OK(hipEventRecord(ctx->ev[(i)], ctx->stream)); \
+    } while (0)
+
+// Enqueue one pass: optional grid build, then neighbours, 2D LP, fallback.
+// With profiling on, the stream is drained after the pass and the time
+// between the stage events is accumulated.
+int run_pass(orca_ctx *ctx, const orca::Plan &pl, const float *grid_pos, const float *grid_vel)
+{
+    STAGE_MARK(0);
+    if (grid_pos) HIP_OK(orca::launch_grid(pl, grid_pos, grid_vel, ctx->stream));
+    STAGE_MARK(1);
+    HIP_OK(orca::launch_knn(pl, ctx->kmax_cur, ctx->stream));
+    STAGE_MARK(2);
+    HIP_OK(orca::launch_lp(pl, ctx->kmax_cur, ctx->stream));
+    STAGE_MARK(3);
+    HIP_OK(orca::launch_fallback(pl, ctx->kmax_cur, ctx->stream));
+    STAGE_MARK(4);
+    if (ctx->profiling) {
+        HIP_OK(hipEventSynchronize(ctx->ev[ORCA_PROF_STAGES]));
+        for (int i = 0; i < ORCA_PROF_STAGES; ++i) {
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+            ctx->stage_ms[i] += ms;
+        }
+        Counters c;
+        HIP_OK(hipMemcpy(&c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost));
+        ctx->prof_fallback += c.n_fallback;
+        ctx->prof_steps += 1;
+    }
+    return ORCA_OK;
+}
+
+void free_all(orca_ctx *c)
+{
+    for (int i = 0; i <= ORCA_PROF_STAGES; ++i)
+        if (c->ev[i]) {
+            (void)hipEventDestroy(c->ev[i]);
+            c->ev[i] = nullptr;
+        }
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *orca_last_error(const orca_ctx *ctx)
+{
+    return ctx ? ctx->err : "no context";
+}
+
+int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t k_max,
+                int32_t tape_steps, void *hip_stream)
+{
+    if (!out) return ORCA_EINVAL;
+    *out = nullptr;
+    if (max_agents < 1 || max_agents > (int64_t)INT32_MAX / 2 || max_scenes < 1 ||
+        max_scenes > (1 << 24) || k_max < 1 || tape_steps < 0)
+        return ORCA_EINVAL;
+    if (k_max > ORCA_K_LIMIT) return ORCA_ECAPACITY;
+    orca_ctx *ctx = new (std::nothrow) orca_ctx;
+    if (!ctx) return ORCA_ENOMEM;
+    ctx->max_agents = max_agents;
+    ctx->max_scenes = max_scenes;
+    ctx->k_max = k_max;
+    ctx->tape_steps = tape_steps;
+    ctx->stream = (hipStream_t)hip_stream;
+    // cell budget: room for 4 cells per agent plus a margin per scene
+    const int64_t cells = 4 * max_agents + 64 * (int64_t)max_scenes + 4096;
+    ctx->max_cells = (uint32_t)(cells < (int64_t)INT32_MAX - 1 ? cells : (int64_t)INT32_MAX - 1);
+    ctx->n_tiles = (int32_t)((ctx->max_cells + orca::kScanTile - 1) / orca::kScanTile);
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    ctx->fb_blocks = cus * 16;
+
+    auto alloc = [&](void **p, size_t bytes) -> bool {
+        if (hipMalloc(p, bytes < 256 ? 256 : bytes) != hipSuccess) {
+            *p = nullptr;
+            return false;
+        }
+        ctx->allocs.push_back(*p);
+        return true;
+    };
+    const size_t A = (size_t)max_agents, S = (size_t)max_scenes, C = (size_t)ctx->max_cells;
+    bool ok = alloc((void **)&ctx->off, sizeof(int32_t) * (S + 1)) &&
+              alloc((void **)&ctx->sp, sizeof(SceneDev) * S) &&
+              alloc((void **)&ctx->agent_scene, sizeof(int32_t) * A) &&
+              alloc((void **)&ctx->bbox, sizeof(uint32_t) * 4 * S) &&
+              alloc((void **)&ctx->grid, sizeof(GridDev) * S) &&
+              alloc((void **)&ctx->counters, sizeof(Counters)) &&
+              alloc((void **)&ctx->key, sizeof(int32_t) * A) &&
+              alloc((void **)&ctx->rank, sizeof(int32_t) * A) &&
+              alloc((void **)&ctx->counts, sizeof(int32_t) * C) &&
+              alloc((void **)&ctx->cell_start, sizeof(int32_t) * (C + 1)) &&
+              alloc((void **)&ctx->partial, sizeof(uint32_t) * (size_t)ctx->n_tiles) &&
+              alloc((void **)&ctx->sorted, sizeof(float4) * A) &&
+              alloc((void **)&ctx->sid, sizeof(int32_t) * A) &&
+              alloc((void **)&ctx->skey, sizeof(int32_t) * A) &&
+              alloc((void **)&ctx->inv, sizeof(int32_t) * A) &&
+              alloc((void **)&ctx->nbr, sizeof(int32_t) * A * (size_t)k_max) &&
+              alloc((void **)&ctx->ncount, sizeof(int32_t) * A) &&
+              alloc((void **)&ctx->fb_list, sizeof(int32_t) * A);
+    if (!ok) {
+        free_all(ctx);
+        delete ctx;
+        return ORCA_ENOMEM;
+    }
+    // counts start at zero and are kept zero between uses by the scan
+    hipError_t e = hipMemsetAsync(ctx->counts, 0, sizeof(int32_t) * C, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->counters, 0, sizeof(Counters), ctx->stream);
+    if (e == hipSuccess) e = orca::launch_scene_map(ctx->off, max_scenes, ctx->agent_scene, 0,
+                                                    ctx->bbox, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        free_all(ctx);
+        delete ctx;
+        return ORCA_EHIP;
+    }
+    *out = ctx;
+    return ORCA_OK;
+}
+
+void orca_destroy(orca_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+}
+
+int orca_set_stream(orca_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return ORCA_EINVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return ORCA_OK;
+}
+
+int orca_build_grid(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
+                    const orca_params *params, const float *pos)
+{
+    if (!ctx) return ORCA_EINVAL;
+    int rc = use_scenes(ctx, n_scenes, scene_offsets, params);
+    if (rc != ORCA_OK) return rc;
+    if (!pos && ctx->n > 0) return fail(ctx, ORCA_EINVAL, "pos must be non-NULL");
+    const orca::Plan pl = make_plan(ctx);
+    HIP_OK(orca::launch_grid(pl, pos, nullptr, ctx->stream));
+    ctx->grid_valid = true;
+    ctx->grid_pos = pos;
+    return ORCA_OK;
+}
+
+int orca_compute_velocities(orca_ctx *ctx, const float *pos, const float *vel,
+                            const float *pref_vel, const float *goals, float *new_vel,
+                            int32_t *nbr_out, uint8_t *lp_status)
+{
+    if (!ctx) return ORCA_EINVAL;
+    if (!ctx->grid_valid || pos != ctx->grid_pos)
+        return fail(ctx, ORCA_ESTATE, "orca_build_grid must be called first on the same pos");
+    if (ctx->n > 0 && (!vel || !new_vel || (!goals && !pref_vel)))
+        return fail(ctx, ORCA_EINVAL, "vel, new_vel and pref_vel (or goals) must be non-NULL");
+    orca::Plan pl = make_plan(ctx);
+    pl.out.new_vel = new_vel;
+    pl.out.pref = const_cast<float *>(pref_vel);
+    pl.out.goals = goals;
+    pl.out.status = lp_status;
+    pl.out.nbr_out = nbr_out;
+    pl.out.krow = ctx->kmax_cur;
+    HIP_OK(orca::launch_fill_vel(pl, vel, ctx->stream));
+    return run_pass(ctx, pl, nullptr, nullptr);
+}
+
+int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
+              const orca_params *params, float *pos, float *vel, float *pref_vel,
+              const float *goals, int32_t n_steps, int32_t save_tape)
+{
+    if (!ctx) return ORCA_EINVAL;
+    if (n_steps < 1) return fail(ctx, ORCA_EINVAL, "n_steps must be >= 1");
+    if (save_tape != 0 && save_tape != 1) return fail(ctx, ORCA_EINVAL, "save_tape must be 0 or 1");
+    int rc = use_scenes(ctx, n_scenes, scene_offsets, params);
+    if (rc != ORCA_OK) return rc;
+    if (ctx->n > 0 && (!pos || !vel || !pref_vel))
+        return fail(ctx, ORCA_EINVAL, "pos, vel and pref_vel must be non-NULL");
+    if (save_tape) {
+        if (goals) return fail(ctx, ORCA_EINVAL, "a recorded step needs fixed preferred velocities");
+        if (n_steps > ctx->tape_steps)
+            return fail(ctx, ORCA_ECAPACITY, "n_steps %d exceeds tape_steps %d", n_steps,
+                        ctx->tape_steps);
+        return fail(ctx, ORCA_ESTATE, "step recording is not available in this build");
+    }
+    orca::Plan pl = make_plan(ctx);
+    pl.out.pos = pos;
+    pl.out.vel = vel;
+    pl.out.pref = pref_vel;
+    pl.out.goals = goals;
+    ctx->grid_valid = false;
+    for (int32_t t = 0; t < n_steps; ++t) {
+        rc = run_pass(ctx, pl, pos, vel);
+        if (rc != ORCA_OK) return rc;
+    }
+    return ORCA_OK;
+}
+
+int orca_profile(orca_ctx *ctx, int32_t enable)
+{
+    if (!ctx) return ORCA_EINVAL;
+    if (enable) {
+        for (int i = 0; i <= ORCA_PROF_STAGES; ++i)
+            if (!ctx->ev[i]) HIP_OK(hipEventCreate(&ctx->ev[i]));
+    }
+    ctx->profiling = enable != 0;
+    for (int i = 0; i < ORCA_PROF_STAGES; ++i) ctx->stage_ms[i] = 0.0;
+    ctx->prof_steps = 0;
+    ctx->prof_fallback = 0;
+    return ORCA_OK;
+}
+
+int orca_profile_read(orca_ctx *ctx, double *stage_ms, int64_t *passes, int64_t *fallback_agents)
+{
+    if (!ctx || !stage_ms) return ORCA_EINVAL;
+    for (int i = 0; i < ORCA_PROF_STAGES; ++i) stage_ms[i] = ctx->stage_ms[i];
+    if (passes) *passes = ctx->prof_steps;
+    if (fallback_agents) *fallback_agents = ctx->prof_fallback;
+    return ORCA_OK;
+}
+
+int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
+                  const float *g_vel_next, float *g_pos, float *g_vel, float *g_pref_vel,
+                  float *g_max_speed, float *g_time_horizon)
+{
+    if (!ctx) return ORCA_EINVAL;
+    (void)tape_step;
+    (void)g_pos_next;
+    (void)g_vel_next;
+    (void)g_pos;
+    (void)g_vel;
+    (void)g_pref_vel;
+    (void)g_max_speed;
+    (void)g_time_horizon;
+    return fail(ctx, ORCA_ESTATE, "no recorded step: step recording is not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// orca_internal.h -- types shared by the kernels and the host side of liborca.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace orca {
+
+constexpr int kScanItems = 16;
+constexpr int kScanBlock = 256;
+constexpr int kScanTile = kScanItems * kScanBlock;  // cells per scan tile
+constexpr int kLpBlock = 64;                        // one wave per LP block
+constexpr double kCellMargin = 1.0 + 1.0 / 1024.0;  // cell side / neighbor_dist
+constexpr double kDelta = 1e-5;  // relaxation of the least-penetration second stage (m/s)
+
+// Per-scene parameters as the kernels read them.
+struct SceneDev {
+    float radius, vmax, nd, tau, dt, pref_speed;
+    float nd2;  // float32 neighbor_dist^2 (the same rounding as every distance test)
+    int32_t k;
+};
+
+// Per-scene grid: cell c = (cx, cy) has key base + cy * nx + cx.
+struct GridDev {
+    double x0, y0, cell;
+    int32_t nx, ny, base, pad;
+};
+
+struct Counters {
+    uint32_t total_cells;
+    uint32_t n_fallback;
+    uint32_t pad[2];
+};
+
+// Where the velocity kernels put their results.  Step mode has pos != nullptr.
+struct OutArgs {
+    float *new_vel;      // [2, N] or nullptr
+    float *pos;          // [2, N] updated in place (step mode) or nullptr
+    float *vel;          // [2, N] (step mode)
+    float *pref;         // [2, N]: read when goals == nullptr, written in step mode with goals
+    const float *goals;  // [2, N] or nullptr
+    uint8_t *status;     // [N] or nullptr
+    int32_t *nbr_out;    // [N, krow] or nullptr
+    int32_t krow;
+};
+
+// Device buffers and sizes of one launch sequence.
+struct Plan {
+    int32_t n, n_scenes, ld, fb_blocks;
+    uint32_t max_cells;
+    const int32_t *off;
+    const SceneDev *sp;
+    int32_t *agent_scene;
+    uint32_t *bbox;
+    GridDev *grid;
+    Counters *counters;
+    int32_t *key, *rank, *counts, *cell_start;
+    uint32_t *partial;
+    float4 *sorted;
+    int32_t *sid, *skey, *inv;
+    int32_t *nbr, *ncount, *fb_list;
+    OutArgs out;
+};
+
+hipError_t launch_scene_map(const int32_t *off, int32_t n_scenes, int32_t *agent_scene, int32_t n,
+                            uint32_t *bbox, hipStream_t st);
+hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, hipStream_t st);
+hipError_t launch_fill_vel(const Plan &pl, const float *vel, hipStream_t st);
+hipError_t launch_knn(const Plan &pl, int kmax, hipStream_t st);
+hipError_t launch_lp(const Plan &pl, int kmax, hipStream_t st);
+hipError_t launch_fallback(const Plan &pl, int kmax, hipStream_t st);
+
+}  // namespace orca

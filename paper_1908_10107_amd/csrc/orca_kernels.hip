@@ -1,0 +1,914 @@
+// orca_kernels.hip -- gfx950 kernels of the ORCA crowd step.
+//
+// One step, in launch order (all on one stream, no host synchronisation):
+//   k_bbox        per-scene bounding box of the positions (ordered-int atomics)
+//   k_grid        per-scene cell size / origin / dimensions and the cell-key
+//                 base of every scene (one block)
+//   k_key         cell key of every agent and its rank inside the cell
+//                 (histogram by atomic increment)
+//   k_scan_sums   per-tile sums of the cell counts
+//   k_scan_apply  exclusive scan -> cell_start, counts cleared for the next step
+//   k_scatter     counting-sort scatter: agents into cell order (float4 x,y,vx,vy)
+//   k_knn         3x3-cell gather, K nearest by float32 squared distance held as
+//                 packed 64-bit keys in registers
+//   k_lp          float64 half-planes in LDS, incremental 2D LP; feasible agents
+//                 write their result, the rest are appended to a fallback list
+//   k_fallback    persistent over the fallback list: least-penetration 3D LP,
+//                 then the 2D LP on the relaxed half-planes
+// Messages: section 3 / Fig. 2 (binning, radius filter); half-planes: Fig. 1;
+// LP and its infeasible case: section 3.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "orca_internal.h"
+
+namespace orca {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint32_t ord_from_float(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float float_from_ord(uint32_t o)
+{
+    uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    return __uint_as_float(u);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_reduce_min(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_reduce_max(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_reduce_sum_u32(uint32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Squared distance in float32 with every operation rounded on its own (no
+// fused multiply-add): the neighbour set is decided by this value.
+__device__ __forceinline__ float dist2_f32(float xi, float yi, float xj, float yj)
+{
+#pragma clang fp contract(off)
+    const float dx = xj - xi;
+    const float dy = yj - yi;
+    const float sx = dx * dx;
+    const float sy = dy * dy;
+    return sx + sy;
+}
+
+// ------------------------------------------------------------------ grid
+
+__global__ void k_scene_of_agent(const int32_t *__restrict__ off, int32_t n_scenes,
+                                 int32_t *__restrict__ agent_scene, int32_t n)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t lo = 0, hi = n_scenes - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    agent_scene[i] = lo;
+}
+
+__global__ void k_reset_bbox(uint32_t *__restrict__ bbox, int32_t n_scenes)
+{
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_scenes) return;
+    bbox[4 * s + 0] = 0xffffffffu;
+    bbox[4 * s + 1] = 0xffffffffu;
+    bbox[4 * s + 2] = 0u;
+    bbox[4 * s + 3] = 0u;
+}
+
+// Bounding box per scene.  A block whose agents all belong to one scene
+// reduces in registers/LDS and issues four atomics; a block that straddles
+// scenes falls back to per-agent atomics.
+__global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ pos, int32_t n,
+                                              const int32_t *__restrict__ agent_scene,
+                                              uint32_t *__restrict__ bbox)
+{
+    __shared__ uint32_t red[4][4];
+    const int32_t first = blockIdx.x * blockDim.x;
+    const int32_t last = min(first + (int32_t)blockDim.x, n) - 1;
+    const int32_t i = first + threadIdx.x;
+    const bool live = i < n;
+    const float x = live ? pos[i] : 0.f;
+    const float y = live ? pos[n + i] : 0.f;
+    const int32_t s0 = agent_scene[first];
+    const int32_t s1 = agent_scene[last];
+    if (s0 != s1) {
+        if (live) {
+            const int32_t s = agent_scene[i];
+            atomicMin(&bbox[4 * s + 0], ord_from_float(x));
+            atomicMin(&bbox[4 * s + 1], ord_from_float(y));
+            atomicMax(&bbox[4 * s + 2], ord_from_float(x));
+            atomicMax(&bbox[4 * s + 3], ord_from_float(y));
+        }
+        return;
+    }
+    uint32_t mnx = live ? ord_from_float(x) : 0xffffffffu;
+    uint32_t mny = live ? ord_from_float(y) : 0xffffffffu;
+    uint32_t mxx = live ? ord_from_float(x) : 0u;
+    uint32_t mxy = live ? ord_from_float(y) : 0u;
+    mnx = wave_reduce_min(mnx);
+    mny = wave_reduce_min(mny);
+    mxx = wave_reduce_max(mxx);
+    mxy = wave_reduce_max(mxy);
+    const int32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        red[wave][0] = mnx;
+        red[wave][1] = mny;
+        red[wave][2] = mxx;
+        red[wave][3] = mxy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int32_t nw = (blockDim.x + 63) >> 6;
+        for (int32_t w = 1; w < nw; ++w) {
+            mnx = min(mnx, red[w][0]);
+            mny = min(mny, red[w][1]);
+            mxx = max(mxx, red[w][2]);
+            mxy = max(mxy, red[w][3]);
+        }
+        atomicMin(&bbox[4 * s0 + 0], mnx);
+        atomicMin(&bbox[4 * s0 + 1], mny);
+        atomicMax(&bbox[4 * s0 + 2], mxx);
+        atomicMax(&bbox[4 * s0 + 3], mxy);
+    }
+}
+
+// Grid of every scene.  Cells are square, at least neighbor_dist * (1 + 2^-10)
+// wide, so two agents closer than neighbor_dist (also after float32 rounding
+// of their squared distance) always sit in the same or adjacent cells.  If the
+// total number of cells would exceed the budget, all cells are widened by a
+// common factor (more candidates per agent, same neighbours).  Also resets
+// the bounding-box accumulators and the fallback counter for the next use.
+__global__ __launch_bounds__(256) void k_grid(int32_t n_scenes, const int32_t *__restrict__ off,
+                                              const SceneDev *__restrict__ sp,
+                                              uint32_t *__restrict__ bbox,
+                                              GridDev *__restrict__ grid,
+                                              Counters *__restrict__ counters, uint32_t max_cells)
+{
+    __shared__ unsigned long long red[4];
+    double f = 1.0;
+    for (int iter = 0; iter < 24; ++iter) {
+        unsigned long long local = 0;
+        for (int32_t s = threadIdx.x; s < n_scenes; s += blockDim.x) {
+            GridDev g;
+            const float x0 = float_from_ord(bbox[4 * s + 0]);
+            const float y0 = float_from_ord(bbox[4 * s + 1]);
+            const float x1 = float_from_ord(bbox[4 * s + 2]);
+            const float y1 = float_from_ord(bbox[4 * s + 3]);
+            const double ex = (double)x1 - (double)x0, ey = (double)y1 - (double)y0;
+            g.cell = (double)sp[s].nd * kCellMargin * f;
+            const bool ok = off[s + 1] > off[s] && isfinite(ex) && isfinite(ey) && ex >= 0.0 &&
+                            ey >= 0.0 && iter < 23;
+            if (ok) {
+                g.x0 = x0;
+                g.y0 = y0;
+                const double nxd = floor(ex / g.cell) + 1.0, nyd = floor(ey / g.cell) + 1.0;
+                g.nx = (int32_t)fmin(nxd, (double)(1 << 22));
+                g.ny = (int32_t)fmin(nyd, (double)(1 << 22));
+            } else {
+                // empty, non-finite, or out of budget: one cell holds the whole scene
+                g.x0 = 0.0;
+                g.y0 = 0.0;
+                g.cell = 1e300;
+                g.nx = 1;
+                g.ny = 1;
+            }
+            g.base = 0;
+            g.pad = 0;
+            grid[s] = g;
+            local += (unsigned long long)g.nx * (unsigned long long)g.ny;
+        }
+        for (int o = 32; o > 0; o >>= 1) local += __shfl_xor(local, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = local;
+        __syncthreads();
+        const unsigned long long total = red[0] + red[1] + red[2] + red[3];
+        __syncthreads();
+        if (total <= (unsigned long long)max_cells) break;
+        f *= sqrt((double)total / (double)max_cells) * 1.05;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t base = 0;
+        for (int32_t s = 0; s < n_scenes; ++s) {
+            grid[s].base = (int32_t)base;
+            base += (uint32_t)grid[s].nx * (uint32_t)grid[s].ny;
+        }
+        counters->total_cells = base;
+        counters->n_fallback = 0;
+    }
+    __syncthreads();
+    for (int32_t s = threadIdx.x; s < n_scenes; s += blockDim.x) {
+        bbox[4 * s + 0] = 0xffffffffu;
+        bbox[4 * s + 1] = 0xffffffffu;
+        bbox[4 * s + 2] = 0u;
+        bbox[4 * s + 3] = 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_key(const float *__restrict__ pos, int32_t n,
+                                             const int32_t *__restrict__ agent_scene,
+                                             const GridDev *__restrict__ grid,
+                                             int32_t *__restrict__ key,
+                                             int32_t *__restrict__ rank,
+                                             int32_t *__restrict__ counts)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const GridDev g = grid[agent_scene[i]];
+    double fx = floor(((double)pos[i] - g.x0) / g.cell);
+    double fy = floor(((double)pos[n + i] - g.y0) / g.cell);
+    fx = fmin(fmax(fx, 0.0), (double)(g.nx - 1));
+    fy = fmin(fmax(fy, 0.0), (double)(g.ny - 1));
+    const int32_t k = g.base + (int32_t)fy * g.nx + (int32_t)fx;
+    key[i] = k;
+    rank[i] = atomicAdd(&counts[k], 1);
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(const int32_t *__restrict__ counts,
+                                                          const Counters *__restrict__ counters,
+                                                          uint32_t *__restrict__ partial)
+{
+    __shared__ uint32_t red[kScanBlock / 64];
+    const uint32_t total = counters->total_cells;
+    const uint32_t base = blockIdx.x * kScanTile;
+    if (base >= total) {
+        if (threadIdx.x == 0) partial[blockIdx.x] = 0;
+        return;
+    }
+    uint32_t s = 0;
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        const uint32_t c = base + t * kScanBlock + threadIdx.x;
+        if (c < total) s += (uint32_t)counts[c];
+    }
+    s = wave_reduce_sum_u32(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kScanBlock / 64; ++w) t += red[w];
+        partial[blockIdx.x] = t;
+    }
+}
+
+// cell_start[c] = sum of counts before c; cell_start[total] = n.  Counts are
+// zeroed after reading so the next histogram starts from zero.
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(int32_t *__restrict__ counts,
+                                                           const Counters *__restrict__ counters,
+                                                           const uint32_t *__restrict__ partial,
+                                                           int32_t *__restrict__ cell_start,
+                                                           int32_t n)
+{
+    __shared__ uint32_t wsum[kScanBlock / 64];
+    __shared__ uint32_t s_prefix;
+    const uint32_t total = counters->total_cells;
+    const uint32_t base = blockIdx.x * kScanTile;
+    if (blockIdx.x == 0 && threadIdx.x == 0) cell_start[total] = n;
+    if (base >= total) return;
+    // prefix of the earlier tiles
+    uint32_t p = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kScanBlock) p += partial[b];
+    p = wave_reduce_sum_u32(p);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = p;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kScanBlock / 64; ++w) t += wsum[w];
+        s_prefix = t;
+    }
+    __syncthreads();
+    // each thread owns kScanItems consecutive cells
+    const uint32_t c0 = base + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t run = 0;
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        const uint32_t c = c0 + t;
+        v[t] = c < total ? (uint32_t)counts[c] : 0u;
+        run += v[t];
+    }
+    // exclusive scan of the per-thread sums across the block
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = run;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    __syncthreads();
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t wprefix = 0;
+    for (int w = 0; w < wave; ++w) wprefix += wsum[w];
+    uint32_t acc = s_prefix + wprefix + inc - run;
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        const uint32_t c = c0 + t;
+        if (c < total) {
+            cell_start[c] = (int32_t)acc;
+            counts[c] = 0;
+        }
+        acc += v[t];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const float *__restrict__ pos,
+                                                 const float *__restrict__ vel, int32_t n,
+                                                 const int32_t *__restrict__ key,
+                                                 const int32_t *__restrict__ rank,
+                                                 const int32_t *__restrict__ cell_start,
+                                                 float4 *__restrict__ sorted,
+                                                 int32_t *__restrict__ sid,
+                                                 int32_t *__restrict__ skey,
+                                                 int32_t *__restrict__ inv)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t k = key[i];
+    const int32_t d = cell_start[k] + rank[i];
+    float4 r;
+    r.x = pos[i];
+    r.y = pos[n + i];
+    r.z = vel ? vel[i] : 0.f;
+    r.w = vel ? vel[n + i] : 0.f;
+    sorted[d] = r;
+    sid[d] = i;
+    skey[d] = k;
+    inv[i] = d;
+}
+
+__global__ __launch_bounds__(256) void k_fill_vel(const float *__restrict__ vel, int32_t n,
+                                                  const int32_t *__restrict__ inv,
+                                                  float4 *__restrict__ sorted)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float2 *dst = reinterpret_cast<float2 *>(&sorted[inv[i]]) + 1;
+    *dst = make_float2(vel[i], vel[n + i]);
+}
+
+// ------------------------------------------------------------------ neighbours
+
+// K nearest of each agent (sorted order s) among the agents of its 3x3 cells,
+// strictly inside neighbor_dist, nearest first, ties by agent id.  The running
+// list holds (float32 bits of d2) << 32 | id, so one 64-bit compare orders by
+// (d2, id).  Writes nbr[k * ld + s] = neighbour id and ncount[s].
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_knn(const float4 *__restrict__ sorted,
+                                             const int32_t *__restrict__ sid,
+                                             const int32_t *__restrict__ skey,
+                                             const int32_t *__restrict__ cell_start,
+                                             const GridDev *__restrict__ grid,
+                                             const int32_t *__restrict__ agent_scene,
+                                             const SceneDev *__restrict__ sp, int32_t n,
+                                             int32_t *__restrict__ nbr, int32_t ld,
+                                             int32_t *__restrict__ ncount,
+                                             Counters *__restrict__ counters)
+{
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    // the fallback list of this velocity pass starts empty (k_lp runs after us)
+    if (s == 0) counters->n_fallback = 0;
+    if (s >= n) return;
+    const float4 me = sorted[s];
+    const int32_t sc = agent_scene[sid[s]];
+    const GridDev g = grid[sc];
+    const int32_t K = sp[sc].k;
+    const float nd2 = sp[sc].nd2;
+    if (K == 0) {
+        ncount[s] = 0;
+        return;
+    }
+    const int32_t c = skey[s] - g.base;
+    const int32_t cy = c / g.nx, cx = c - cy * g.nx;
+    uint64_t best[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) best[k] = ~0ull;
+    uint64_t worst = ~0ull;  // current K-th entry
+    const int32_t c0 = max(cx - 1, 0), c1 = min(cx + 1, g.nx - 1);
+    for (int32_t dy = -1; dy <= 1; ++dy) {
+        const int32_t row = cy + dy;
+        if (row < 0 || row >= g.ny) continue;
+        const int32_t rb = g.base + row * g.nx;
+        const int32_t beg = cell_start[rb + c0], end = cell_start[rb + c1 + 1];
+        for (int32_t j = beg; j < end; ++j) {
+            const float4 o = sorted[j];
+            const float d2 = dist2_f32(me.x, me.y, o.x, o.y);
+            if (d2 < nd2 && j != s) {
+                const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)sid[j];
+                if (key < worst) {
+#pragma unroll
+                    for (int k = KMAX - 1; k > 0; --k) {
+                        const bool shift = key < best[k - 1];
+                        const bool here = key < best[k];
+                        best[k] = shift ? best[k - 1] : (here ? key : best[k]);
+                    }
+                    best[0] = key < best[0] ? key : best[0];
+                    if (K == KMAX) {
+                        worst = best[KMAX - 1];
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < KMAX; ++k)
+                            if (k == K - 1) worst = best[k];
+                    }
+                }
+            }
+        }
+    }
+    int32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        if (k < K && best[k] != ~0ull) {
+            nbr[(int64_t)k * ld + s] = (int32_t)(uint32_t)(best[k] & 0xffffffffu);
+            cnt = k + 1;
+        }
+    }
+    ncount[s] = cnt;
+}
+
+// ------------------------------------------------------------------ half-planes
+
+// Shortest change u of the relative velocity V = v_i - v_j out of the velocity
+// obstacle of neighbour j (relative position P = x_j - x_i, combined radius R,
+// look-ahead tau) and the outward normal n at V + u (Fig. 1(b)-(c)).  A pair
+// already closer than R uses the one-step disc D(P/dt, R/dt).  No fused
+// multiply-add: the operations are rounded one by one.
+__device__ __forceinline__ void obstacle_exit(double Px, double Py, double Vx, double Vy, double R,
+                                              double tau, double dt, bool i_first, double &ux,
+                                              double &uy, double &nx, double &ny)
+{
+#pragma clang fp contract(off)
+    const double dist2 = Px * Px + Py * Py;
+    const double R2 = R * R;
+    if (dist2 > R2) {
+        const double wx = Vx - Px / tau, wy = Vy - Py / tau;
+        const double w2 = wx * wx + wy * wy;
+        const double wP = wx * Px + wy * Py;
+        if (wP < 0.0 && wP * wP > R2 * w2) {
+            // V faces the cut-off arc
+            const double wl = sqrt(w2);
+            nx = wx / wl;
+            ny = wy / wl;
+            const double f = R / tau - wl;
+            ux = f * nx;
+            uy = f * ny;
+            return;
+        }
+        // nearest boundary point on a tangent leg; left if V is left of P
+        const double L = sqrt(dist2 - R2);
+        double lx, ly;
+        if (Px * wy - Py * wx > 0.0) {
+            lx = (Px * L - Py * R) / dist2;
+            ly = (Px * R + Py * L) / dist2;
+            nx = -ly;
+            ny = lx;
+        } else {
+            lx = (Px * L + Py * R) / dist2;
+            ly = (-Px * R + Py * L) / dist2;
+            nx = ly;
+            ny = -lx;
+        }
+        const double sdot = Vx * lx + Vy * ly;
+        ux = sdot * lx - Vx;
+        uy = sdot * ly - Vy;
+        return;
+    }
+    const double wx = Vx - Px / dt, wy = Vy - Py / dt;
+    const double wl = sqrt(wx * wx + wy * wy);
+    if (wl > 0.0) {
+        nx = wx / wl;
+        ny = wy / wl;
+    } else if (dist2 > 0.0) {
+        const double pl = sqrt(dist2);
+        nx = -Px / pl;
+        ny = -Py / pl;
+    } else {
+        nx = i_first ? 1.0 : -1.0;
+        ny = 0.0;
+    }
+    const double f = R / dt - wl;
+    ux = f * nx;
+    uy = f * ny;
+}
+
+// Constraint store of one lane: element k at [k * kLpBlock + lane] of the
+// block's LDS arrays.  Half-plane k is {v : n_k . v >= b_k}.
+struct Lane {
+    double *nx, *ny, *b;
+    __device__ __forceinline__ double NX(int k) const { return nx[k * kLpBlock]; }
+    __device__ __forceinline__ double NY(int k) const { return ny[k * kLpBlock]; }
+    __device__ __forceinline__ double B(int k) const { return b[k * kLpBlock]; }
+};
+
+// Incremental 2D LP: the point of the disc |v| <= vmax and of the half-planes
+// n_k.v >= b_k - relax closest to vhat.  Constraints enter one by one; when
+// the current point violates constraint k the new optimum lies on its line,
+// found by a 1D program against the disc and constraints 0..k-1.  Returns -1
+// (feasible, v set) or the first k whose 1D program is empty (v = the optimum
+// over constraints 0..k-1).
+__device__ int lp2_project(const Lane &L, int m, double relax, double vmax, double vhx, double vhy,
+                           double &vx, double &vy)
+{
+    const double vm2 = vmax * vmax;
+    const double vh2 = vhx * vhx + vhy * vhy;
+    if (vh2 > vm2) {
+        const double sc = vmax / sqrt(vh2);
+        vx = vhx * sc;
+        vy = vhy * sc;
+    } else {
+        vx = vhx;
+        vy = vhy;
+    }
+    for (int k = 0; k < m; ++k) {
+        const double nkx = L.NX(k), nky = L.NY(k), bk = L.B(k) - relax;
+        if (nkx * vx + nky * vy >= bk) continue;
+        double h2 = vm2 - bk * bk;
+        if (h2 < 0.0) {
+            if (bk > 0.0) return k;  // the line misses the disc on the far side
+            h2 = 0.0;
+        }
+        const double h = sqrt(h2);
+        double lo = -h, hi = h;
+        // line k: p(t) = bk n_k + t d_k with d_k = (-nky, nkx)
+        for (int j = 0; j < k; ++j) {
+            const double njx = L.NX(j), njy = L.NY(j), bj = L.B(j) - relax;
+            const double den = njy * nkx - njx * nky;           // n_j . d_k
+            const double num = bj - bk * (njx * nkx + njy * nky); // b_j - n_j . (bk n_k)
+            if (den > 0.0) lo = fmax(lo, num / den);
+            else if (den < 0.0) hi = fmin(hi, num / den);
+            else if (num > 0.0) return k;
+        }
+        if (lo > hi) return k;
+        const double t = fmin(fmax(nkx * vhy - nky * vhx, lo), hi);  // d_k . vhat, clamped
+        vx = bk * nkx - t * nky;
+        vy = bk * nky + t * nkx;
+    }
+    return -1;
+}
+
+// Projected constraint i of the plane-k subproblem: i = -1 is "no negative
+// penetration" (-n_k . v >= -b_k), i >= 0 is "constraint i penetrates no more
+// than k" ((n_i - n_k) . v >= b_i - b_k).
+__device__ __forceinline__ void plane_row(const Lane &L, int i, double nkx, double nky, double bk,
+                                          double &mx, double &my, double &c)
+{
+    if (i < 0) {
+        mx = -nkx;
+        my = -nky;
+        c = -bk;
+    } else {
+        mx = L.NX(i) - nkx;
+        my = L.NY(i) - nky;
+        c = L.B(i) - bk;
+    }
+}
+
+// Maximise n_k . v over the disc and the projected constraints -1..k-1
+// (incremental, as lp2_project but with a linear objective).  Returns false
+// if the subproblem is empty.
+__device__ bool lp2_plane(const Lane &L, int k, double nkx, double nky, double bk, double vmax,
+                          double &vx, double &vy)
+{
+    const double vm2 = vmax * vmax;
+    vx = vmax * nkx;
+    vy = vmax * nky;
+    for (int i = -1; i < k; ++i) {
+        double mx, my, ci;
+        plane_row(L, i, nkx, nky, bk, mx, my, ci);
+        if (mx * vx + my * vy >= ci) continue;
+        const double mm = mx * mx + my * my;
+        if (mm == 0.0) {
+            if (ci > 0.0) return false;
+            continue;
+        }
+        const double disc = vm2 * mm - ci * ci;
+        if (disc < 0.0) return false;
+        const double hs = sqrt(disc) / mm;
+        double lo = -hs, hi = hs;
+        const double p0x = ci * mx / mm, p0y = ci * my / mm;
+        // line i: p(s) = p0 + s (-my, mx)
+        for (int j = -1; j < i; ++j) {
+            double ax, ay, cj;
+            plane_row(L, j, nkx, nky, bk, ax, ay, cj);
+            const double den = ay * mx - ax * my;
+            const double num = cj - (ax * p0x + ay * p0y);
+            if (den > 0.0) lo = fmax(lo, num / den);
+            else if (den < 0.0) hi = fmin(hi, num / den);
+            else if (num > 0.0) return false;
+        }
+        if (lo > hi) return false;
+        const double slope = nky * mx - nkx * my;  // n_k . (-my, mx)
+        const double sbest = slope > 0.0 ? hi : (slope < 0.0 ? lo : fmin(fmax(0.0, lo), hi));
+        vx = p0x - sbest * my;
+        vy = p0y + sbest * mx;
+    }
+    return true;
+}
+
+// Least penetration d* = min over the disc of max_k (b_k - n_k . v), by an
+// incremental 3D program in (v, t) with t >= 0, starting from a point that
+// satisfies constraints 0..start-1 (so t = 0 is optimal for them).  When
+// constraint k is violated beyond the current t, the new optimum has
+// t = b_k - n_k . v: maximise n_k . v on that plane.
+__device__ double lp3_least_penetration(const Lane &L, int m, int start, double vmax, double &vx,
+                                        double &vy)
+{
+    double t = 0.0;
+    for (int k = start; k < m; ++k) {
+        const double nkx = L.NX(k), nky = L.NY(k), bk = L.B(k);
+        if (nkx * vx + nky * vy + t >= bk) continue;
+        double wx, wy;
+        if (lp2_plane(L, k, nkx, nky, bk, vmax, wx, wy)) {
+            vx = wx;
+            vy = wy;
+            t = fmax(bk - (nkx * vx + nky * vy), 0.0);
+        }
+    }
+    return t;
+}
+
+// Load agent s's neighbours, build the half-planes into the lane's LDS column.
+template <int KMAX>
+__device__ __forceinline__ int build_constraints(const Lane &L, int32_t s, int32_t id, float4 me,
+                                                 const SceneDev &p, const float4 *__restrict__ sorted,
+                                                 const int32_t *__restrict__ inv,
+                                                 const int32_t *__restrict__ nbr, int32_t ld,
+                                                 const int32_t *__restrict__ ncount,
+                                                 int32_t *__restrict__ nbr_out, int32_t krow)
+{
+    const int32_t m = ncount[s];
+    const double R = 2.0 * (double)p.radius;
+    const double tau = (double)p.tau, dt = (double)p.dt;
+    const double vix = (double)me.z, viy = (double)me.w;
+    for (int k = 0; k < m; ++k) {
+        const int32_t jid = nbr[(int64_t)k * ld + s];
+        const float4 o = sorted[inv[jid]];
+        const double Px = (double)o.x - (double)me.x, Py = (double)o.y - (double)me.y;
+        const double Vx = vix - (double)o.z, Vy = viy - (double)o.w;
+        double ux, uy, nx, ny;
+        obstacle_exit(Px, Py, Vx, Vy, R, tau, dt, id < jid, ux, uy, nx, ny);
+        const double qx = vix + 0.5 * ux, qy = viy + 0.5 * uy;
+        L.nx[k * kLpBlock] = nx;
+        L.ny[k * kLpBlock] = ny;
+        L.b[k * kLpBlock] = nx * qx + ny * qy;
+        if (nbr_out) nbr_out[(int64_t)id * krow + k] = jid;
+    }
+    if (nbr_out)
+        for (int k = m; k < krow; ++k) nbr_out[(int64_t)id * krow + k] = -1;
+    return m;
+}
+
+__device__ __forceinline__ void preferred_velocity(const SceneDev &p, float4 me, int32_t id,
+                                                   int32_t n, const float *__restrict__ pref,
+                                                   const float *__restrict__ goals, double &vhx,
+                                                   double &vhy)
+{
+#pragma clang fp contract(off)
+    if (goals) {
+        // walking speed toward the goal; the last step lands on it
+        const double ex = (double)goals[id] - (double)me.x;
+        const double ey = (double)goals[n + id] - (double)me.y;
+        const double el = sqrt(ex * ex + ey * ey);
+        const double s = (double)p.pref_speed, dt = (double)p.dt;
+        if (el > s * dt) {
+            vhx = s * ex / el;
+            vhy = s * ey / el;
+        } else {
+            vhx = ex / dt;
+            vhy = ey / dt;
+        }
+    } else {
+        vhx = (double)pref[id];
+        vhy = (double)pref[n + id];
+    }
+}
+
+__device__ __forceinline__ void write_result(const OutArgs &o, const SceneDev &p, float4 me,
+                                             int32_t id, int32_t n, double vx, double vy,
+                                             double vhx, double vhy, uint8_t status)
+{
+#pragma clang fp contract(off)
+    if (o.new_vel) {
+        o.new_vel[id] = (float)vx;
+        o.new_vel[n + id] = (float)vy;
+    }
+    if (o.pos) {
+        const double dt = (double)p.dt;
+        o.pos[id] = (float)((double)me.x + dt * vx);
+        o.pos[n + id] = (float)((double)me.y + dt * vy);
+        o.vel[id] = (float)vx;
+        o.vel[n + id] = (float)vy;
+        if (o.goals) {
+            o.pref[id] = (float)vhx;
+            o.pref[n + id] = (float)vhy;
+        }
+    }
+    if (o.status) o.status[id] = status;
+}
+
+// One lane per agent in cell order.  Feasible agents finish here; agents whose
+// 2D program is empty are appended to the fallback list (one atomic per wave).
+template <int KMAX>
+__global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sorted,
+                                                 const int32_t *__restrict__ sid,
+                                                 const int32_t *__restrict__ inv,
+                                                 const int32_t *__restrict__ agent_scene,
+                                                 const SceneDev *__restrict__ sp, int32_t n,
+                                                 const int32_t *__restrict__ nbr, int32_t ld,
+                                                 const int32_t *__restrict__ ncount,
+                                                 OutArgs out, int32_t *__restrict__ fb_list,
+                                                 Counters *__restrict__ counters)
+{
+    __shared__ double s_nx[KMAX * kLpBlock];
+    __shared__ double s_ny[KMAX * kLpBlock];
+    __shared__ double s_b[KMAX * kLpBlock];
+    const int32_t s = blockIdx.x * kLpBlock + threadIdx.x;
+    bool need_fb = false;
+    if (s < n) {
+        const Lane L{s_nx + threadIdx.x, s_ny + threadIdx.x, s_b + threadIdx.x};
+        const float4 me = sorted[s];
+        const int32_t id = sid[s];
+        const SceneDev p = sp[agent_scene[id]];
+        double vhx, vhy;
+        preferred_velocity(p, me, id, n, out.pref, out.goals, vhx, vhy);
+        const int m = build_constraints<KMAX>(L, s, id, me, p, sorted, inv, nbr, ld, ncount,
+                                              out.nbr_out, out.krow);
+        double vx, vy;
+        const int fail = lp2_project(L, m, 0.0, (double)p.vmax, vhx, vhy, vx, vy);
+        if (fail < 0) write_result(out, p, me, id, n, vx, vy, vhx, vhy, 0);
+        else need_fb = true;
+    }
+    const uint64_t mask = __ballot(need_fb);
+    if (mask) {
+        const uint32_t lane = threadIdx.x & 63;
+        const uint32_t before = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        uint32_t slot0 = 0;
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        if ((int)lane == leader) slot0 = atomicAdd(&counters->n_fallback, (uint32_t)__popcll(mask));
+        slot0 = __shfl(slot0, leader, 64);
+        if (need_fb) fb_list[slot0 + before] = s;
+    }
+}
+
+// Persistent over the fallback list: rebuild the half-planes, rerun the 2D
+// program to its first empty step, find the least penetration d*, then take
+// the point closest to vhat among those within d* + delta of every half-plane.
+template <int KMAX>
+__global__ __launch_bounds__(kLpBlock) void k_fallback(const float4 *__restrict__ sorted,
+                                                       const int32_t *__restrict__ sid,
+                                                       const int32_t *__restrict__ inv,
+                                                       const int32_t *__restrict__ agent_scene,
+                                                       const SceneDev *__restrict__ sp,
+                                                       int32_t n, const int32_t *__restrict__ nbr,
+                                                       int32_t ld,
+                                                       const int32_t *__restrict__ ncount,
+                                                       OutArgs out,
+                                                       const int32_t *__restrict__ fb_list,
+                                                       const Counters *__restrict__ counters)
+{
+    __shared__ double s_nx[KMAX * kLpBlock];
+    __shared__ double s_ny[KMAX * kLpBlock];
+    __shared__ double s_b[KMAX * kLpBlock];
+    const uint32_t count = counters->n_fallback;
+    const Lane L{s_nx + threadIdx.x, s_ny + threadIdx.x, s_b + threadIdx.x};
+    for (uint32_t idx = blockIdx.x * kLpBlock + threadIdx.x; idx < count;
+         idx += gridDim.x * kLpBlock) {
+        const int32_t s = fb_list[idx];
+        const float4 me = sorted[s];
+        const int32_t id = sid[s];
+        const SceneDev p = sp[agent_scene[id]];
+        double vhx, vhy;
+        preferred_velocity(p, me, id, n, out.pref, out.goals, vhx, vhy);
+        const int m = build_constraints<KMAX>(L, s, id, me, p, sorted, inv, nbr, ld, ncount,
+                                              nullptr, 0);
+        const double vmax = (double)p.vmax;
+        double vx, vy;
+        const int fail = lp2_project(L, m, 0.0, vmax, vhx, vhy, vx, vy);
+        uint8_t status = 0;
+        if (fail >= 0) {
+            status = 1;
+            const double d = lp3_least_penetration(L, m, fail, vmax, vx, vy);
+            double wx, wy;
+            if (lp2_project(L, m, d + kDelta, vmax, vhx, vhy, wx, wy) < 0) {
+                vx = wx;
+                vy = wy;
+            }
+        }
+        write_result(out, p, me, id, n, vx, vy, vhx, vhy, status);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int KMAX>
+hipError_t launch_knn_k(const Plan &pl, hipStream_t st)
+{
+    const int32_t n = pl.n;
+    hipLaunchKernelGGL(k_knn<KMAX>, dim3((n + 255) / 256), dim3(256), 0, st, pl.sorted, pl.sid,
+                       pl.skey, pl.cell_start, pl.grid, pl.agent_scene, pl.sp, n, pl.nbr, pl.ld,
+                       pl.ncount, pl.counters);
+    return hipGetLastError();
+}
+
+template <int KMAX>
+hipError_t launch_lp_k(const Plan &pl, hipStream_t st)
+{
+    const int32_t n = pl.n;
+    const int32_t gl = (n + kLpBlock - 1) / kLpBlock;
+    hipLaunchKernelGGL(k_lp<KMAX>, dim3(gl), dim3(kLpBlock), 0, st, pl.sorted, pl.sid, pl.inv,
+                       pl.agent_scene, pl.sp, n, pl.nbr, pl.ld, pl.ncount, pl.out, pl.fb_list,
+                       pl.counters);
+    return hipGetLastError();
+}
+
+template <int KMAX>
+hipError_t launch_fallback_k(const Plan &pl, hipStream_t st)
+{
+    const int32_t n = pl.n;
+    const int32_t gl = (n + kLpBlock - 1) / kLpBlock;
+    const int32_t gf = min(gl, pl.fb_blocks);
+    hipLaunchKernelGGL(k_fallback<KMAX>, dim3(gf), dim3(kLpBlock), 0, st, pl.sorted, pl.sid,
+                       pl.inv, pl.agent_scene, pl.sp, n, pl.nbr, pl.ld, pl.ncount, pl.out,
+                       pl.fb_list, pl.counters);
+    return hipGetLastError();
+}
+
+// The neighbour-list length picks the register / LDS footprint.
+#define ORCA_DISPATCH_K(fn)                                  \
+    if (pl.n == 0) return hipSuccess;                        \
+    if (kmax <= 10) return fn<10>(pl, st);                   \
+    if (kmax <= 16) return fn<16>(pl, st);                   \
+    return fn<32>(pl, st);
+
+hipError_t launch_knn(const Plan &pl, int kmax, hipStream_t st) { ORCA_DISPATCH_K(launch_knn_k) }
+hipError_t launch_lp(const Plan &pl, int kmax, hipStream_t st) { ORCA_DISPATCH_K(launch_lp_k) }
+hipError_t launch_fallback(const Plan &pl, int kmax, hipStream_t st)
+{
+    ORCA_DISPATCH_K(launch_fallback_k)
+}
+
+hipError_t launch_scene_map(const int32_t *off, int32_t n_scenes, int32_t *agent_scene, int32_t n,
+                            uint32_t *bbox, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_scene_of_agent, dim3((n + 255) / 256), dim3(256), 0, st, off,
+                           n_scenes, agent_scene, n);
+    hipLaunchKernelGGL(k_reset_bbox, dim3((n_scenes + 255) / 256), dim3(256), 0, st, bbox,
+                       n_scenes);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, hipStream_t st)
+{
+    const int32_t n = pl.n;
+    if (n > 0)
+        hipLaunchKernelGGL(k_bbox, dim3((n + 255) / 256), dim3(256), 0, st, pos, n,
+                           pl.agent_scene, pl.bbox);
+    hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, pl.n_scenes, pl.off, pl.sp, pl.bbox,
+                       pl.grid, pl.counters, pl.max_cells);
+    if (n == 0) return hipGetLastError();
+    hipLaunchKernelGGL(k_key, dim3((n + 255) / 256), dim3(256), 0, st, pos, n, pl.agent_scene,
+                       pl.grid, pl.key, pl.rank, pl.counts);
+    const int32_t tiles = (int32_t)((pl.max_cells + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_sums, dim3(tiles), dim3(kScanBlock), 0, st, pl.counts, pl.counters,
+                       pl.partial);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kScanBlock), 0, st, pl.counts,
+                       pl.counters, pl.partial, pl.cell_start, n);
+    hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, st, pos, vel, n, pl.key,
+                       pl.rank, pl.cell_start, pl.sorted, pl.sid, pl.skey, pl.inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_vel(const Plan &pl, const float *vel, hipStream_t st)
+{
+    if (pl.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_vel, dim3((pl.n + 255) / 256), dim3(256), 0, st, vel, pl.n, pl.inv,
+                       pl.sorted);
+    return hipGetLastError();
+}
+
+}  // namespace orca

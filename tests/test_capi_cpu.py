@@ -1,0 +1,59 @@
+"""Host-side checks of liborca that need no GPU.
+
+The library must load and export every entry point include/orca.h declares;
+calls whose arguments fail host validation must return the documented error
+before anything reaches the device.
+"""
+import ctypes
+import os
+
+import pytest
+
+from paper_1908_10107_amd import orca
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(orca.LIB_PATH):
+        from paper_1908_10107_amd import build_lib
+        build_lib.build()
+    return orca.load()
+
+
+def test_header_declares_the_five_entry_points():
+    syms = orca.header_symbols()
+    for s in ("orca_create", "orca_build_grid", "orca_compute_velocities", "orca_step",
+              "orca_backward"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for s in orca.header_symbols():
+        assert hasattr(lib, s), s
+
+
+def test_create_rejects_bad_sizes_without_touching_the_gpu(lib):
+    h = ctypes.c_void_p(123)
+    assert lib.orca_create(None, 10, 1, 8, 0, None) == orca.EINVAL
+    assert lib.orca_create(ctypes.byref(h), 0, 1, 8, 0, None) == orca.EINVAL
+    assert h.value is None
+    assert lib.orca_create(ctypes.byref(h), 10, 0, 8, 0, None) == orca.EINVAL
+    assert lib.orca_create(ctypes.byref(h), 10, 1, 0, 0, None) == orca.EINVAL
+    assert lib.orca_create(ctypes.byref(h), 10, 1, 8, -1, None) == orca.EINVAL
+    assert lib.orca_create(ctypes.byref(h), 10, 1, orca.K_LIMIT + 1, 0, None) == orca.ECAPACITY
+    assert lib.orca_create(ctypes.byref(h), 1 << 40, 1, 8, 0, None) == orca.EINVAL
+
+
+def test_null_context_calls(lib):
+    assert lib.orca_last_error(None) == b"no context"
+    assert lib.orca_build_grid(None, 1, None, None, None) == orca.EINVAL
+    assert lib.orca_compute_velocities(None, *([None] * 7)) == orca.EINVAL
+    assert lib.orca_step(None, 1, None, None, None, None, None, None, 1, 0) == orca.EINVAL
+    assert lib.orca_backward(None, 0, *([None] * 7)) == orca.EINVAL
+    assert lib.orca_set_stream(None, None) == orca.EINVAL
+    lib.orca_destroy(None)
+
+
+def test_params_struct_matches_header():
+    # orca_params: six floats and two int32
+    assert ctypes.sizeof(orca.OrcaParams) == 32
