@@ -32,13 +32,16 @@ struct orca_ctx {
     SceneDev *sp = nullptr;
     int32_t *agent_scene = nullptr;
     uint32_t *bbox = nullptr;
+    int2 *chunks = nullptr;
+    int64_t max_chunks = 0;
     GridDev *grid = nullptr;
     Counters *counters = nullptr;
     int32_t *key = nullptr, *rank = nullptr, *counts = nullptr, *cell_start = nullptr;
     uint32_t *partial = nullptr;
     float4 *sorted = nullptr;
     int32_t *sid = nullptr, *skey = nullptr, *inv = nullptr;
-    int32_t *nbr = nullptr, *ncount = nullptr, *fb_list = nullptr;
+    int32_t *nbr = nullptr, *ncount = nullptr;
+    orca::FallbackItem *fb_list = nullptr;
     std::vector<void *> allocs;
 
     // scene set currently on the device
@@ -49,6 +52,7 @@ struct orca_ctx {
     std::vector<orca_params> h_par;
     std::vector<int32_t> h_off32;
     std::vector<SceneDev> h_sp;
+    std::vector<int2> h_chunks;
     bool uploaded = false;
 
     // grid state
@@ -146,6 +150,10 @@ int use_scenes(orca_ctx *ctx, int32_t n_scenes, const int64_t *off, const orca_p
     ctx->h_sp.resize((size_t)n_scenes);
     ctx->kmax_cur = 0;
     for (int32_t s = 0; s <= n_scenes; ++s) ctx->h_off32[s] = (int32_t)off[s];
+    ctx->h_chunks.clear();
+    for (int32_t s = 0; s < n_scenes; ++s)
+        for (int64_t a = off[s]; a < off[s + 1]; a += orca::kBboxChunk)
+            ctx->h_chunks.push_back(make_int2(s, (int32_t)a));
     for (int32_t s = 0; s < n_scenes; ++s) {
         SceneDev d;
         d.radius = par[s].radius;
@@ -164,6 +172,10 @@ int use_scenes(orca_ctx *ctx, int32_t n_scenes, const int64_t *off, const orca_p
                           hipMemcpyHostToDevice, ctx->stream));
     HIP_OK(hipMemcpyAsync(ctx->sp, ctx->h_sp.data(), sizeof(SceneDev) * (size_t)n_scenes,
                           hipMemcpyHostToDevice, ctx->stream));
+    if (!ctx->h_chunks.empty())
+        HIP_OK(hipMemcpyAsync(ctx->chunks, ctx->h_chunks.data(),
+                              sizeof(int2) * ctx->h_chunks.size(), hipMemcpyHostToDevice,
+                              ctx->stream));
     HIP_OK(orca::launch_scene_map(ctx->off, n_scenes, ctx->agent_scene, (int32_t)ctx->n, ctx->bbox,
                                   ctx->stream));
     ctx->uploaded = true;
@@ -183,6 +195,8 @@ orca::Plan make_plan(const orca_ctx *ctx)
     p.sp = ctx->sp;
     p.agent_scene = ctx->agent_scene;
     p.bbox = ctx->bbox;
+    p.chunks = ctx->chunks;
+    p.n_chunks = (int32_t)ctx->h_chunks.size();
     p.grid = ctx->grid;
     p.counters = ctx->counters;
     p.key = ctx->key;
@@ -281,6 +295,8 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
             cus = prop.multiProcessorCount;
     }
     ctx->fb_blocks = cus * 16;
+    // each scene's agents split into chunks of kBboxChunk: at most A / chunk + S chunks
+    ctx->max_chunks = max_agents / orca::kBboxChunk + max_scenes + 1;
 
     auto alloc = [&](void **p, size_t bytes) -> bool {
         if (hipMalloc(p, bytes < 256 ? 256 : bytes) != hipSuccess) {
@@ -295,6 +311,7 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->sp, sizeof(SceneDev) * S) &&
               alloc((void **)&ctx->agent_scene, sizeof(int32_t) * A) &&
               alloc((void **)&ctx->bbox, sizeof(uint32_t) * 4 * S) &&
+              alloc((void **)&ctx->chunks, sizeof(int2) * (size_t)ctx->max_chunks) &&
               alloc((void **)&ctx->grid, sizeof(GridDev) * S) &&
               alloc((void **)&ctx->counters, sizeof(Counters)) &&
               alloc((void **)&ctx->key, sizeof(int32_t) * A) &&
@@ -308,7 +325,7 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->inv, sizeof(int32_t) * A) &&
               alloc((void **)&ctx->nbr, sizeof(int32_t) * A * (size_t)k_max) &&
               alloc((void **)&ctx->ncount, sizeof(int32_t) * A) &&
-              alloc((void **)&ctx->fb_list, sizeof(int32_t) * A);
+              alloc((void **)&ctx->fb_list, sizeof(orca::FallbackItem) * A);
     if (!ok) {
         free_all(ctx);
         delete ctx;

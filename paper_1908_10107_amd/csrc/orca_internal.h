@@ -10,6 +10,7 @@ constexpr int kScanItems = 16;
 constexpr int kScanBlock = 256;
 constexpr int kScanTile = kScanItems * kScanBlock;  // cells per scan tile
 constexpr int kLpBlock = 64;                        // one wave per LP block
+constexpr int kBboxChunk = 8192;                    // agents per bounding-box block
 constexpr double kCellMargin = 1.0 + 1.0 / 1024.0;  // cell side / neighbor_dist
 constexpr double kDelta = 1e-5;  // relaxation of the least-penetration second stage (m/s)
 
@@ -32,6 +33,13 @@ struct Counters {
     uint32_t pad[2];
 };
 
+// An agent whose 2D program was empty: its sorted index, the constraint at
+// which the program failed, and the optimum of the constraints before it.
+struct FallbackItem {
+    int32_t s, fail;
+    double vx, vy;
+};
+
 // Where the velocity kernels put their results.  Step mode has pos != nullptr.
 struct OutArgs {
     float *new_vel;      // [2, N] or nullptr
@@ -46,19 +54,21 @@ struct OutArgs {
 
 // Device buffers and sizes of one launch sequence.
 struct Plan {
-    int32_t n, n_scenes, ld, fb_blocks;
+    int32_t n, n_scenes, ld, fb_blocks, n_chunks;
     uint32_t max_cells;
     const int32_t *off;
     const SceneDev *sp;
     int32_t *agent_scene;
     uint32_t *bbox;
+    const int2 *chunks;  // (scene, first agent) of each bounding-box block
     GridDev *grid;
     Counters *counters;
     int32_t *key, *rank, *counts, *cell_start;
     uint32_t *partial;
     float4 *sorted;
     int32_t *sid, *skey, *inv;
-    int32_t *nbr, *ncount, *fb_list;
+    int32_t *nbr, *ncount;
+    FallbackItem *fb_list;
     OutArgs out;
 };
 

@@ -101,36 +101,27 @@ __global__ void k_reset_bbox(uint32_t *__restrict__ bbox, int32_t n_scenes)
     bbox[4 * s + 3] = 0u;
 }
 
-// Bounding box per scene.  A block whose agents all belong to one scene
-// reduces in registers/LDS and issues four atomics; a block that straddles
-// scenes falls back to per-agent atomics.
+// Bounding box per scene.  Block b reduces chunk b (at most kBboxChunk agents
+// of one scene, listed by the host when the scene set changes) in registers
+// and LDS, then folds it into its scene with four atomics: a 1M-agent scene
+// costs 128 x 4 atomics instead of one set per 256 agents.
 __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ pos, int32_t n,
-                                              const int32_t *__restrict__ agent_scene,
+                                              const int2 *__restrict__ chunks,
+                                              const int32_t *__restrict__ off,
                                               uint32_t *__restrict__ bbox)
 {
     __shared__ uint32_t red[4][4];
-    const int32_t first = blockIdx.x * blockDim.x;
-    const int32_t last = min(first + (int32_t)blockDim.x, n) - 1;
-    const int32_t i = first + threadIdx.x;
-    const bool live = i < n;
-    const float x = live ? pos[i] : 0.f;
-    const float y = live ? pos[n + i] : 0.f;
-    const int32_t s0 = agent_scene[first];
-    const int32_t s1 = agent_scene[last];
-    if (s0 != s1) {
-        if (live) {
-            const int32_t s = agent_scene[i];
-            atomicMin(&bbox[4 * s + 0], ord_from_float(x));
-            atomicMin(&bbox[4 * s + 1], ord_from_float(y));
-            atomicMax(&bbox[4 * s + 2], ord_from_float(x));
-            atomicMax(&bbox[4 * s + 3], ord_from_float(y));
-        }
-        return;
+    const int2 ch = chunks[blockIdx.x];  // (scene, first agent)
+    const int32_t end = min(ch.y + kBboxChunk, off[ch.x + 1]);
+    uint32_t mnx = 0xffffffffu, mny = 0xffffffffu, mxx = 0u, mxy = 0u;
+    for (int32_t i = ch.y + threadIdx.x; i < end; i += blockDim.x) {
+        const uint32_t ox = ord_from_float(pos[i]);
+        const uint32_t oy = ord_from_float(pos[n + i]);
+        mnx = min(mnx, ox);
+        mny = min(mny, oy);
+        mxx = max(mxx, ox);
+        mxy = max(mxy, oy);
     }
-    uint32_t mnx = live ? ord_from_float(x) : 0xffffffffu;
-    uint32_t mny = live ? ord_from_float(y) : 0xffffffffu;
-    uint32_t mxx = live ? ord_from_float(x) : 0u;
-    uint32_t mxy = live ? ord_from_float(y) : 0u;
     mnx = wave_reduce_min(mnx);
     mny = wave_reduce_min(mny);
     mxx = wave_reduce_max(mxx);
@@ -144,17 +135,17 @@ __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ pos, int
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int32_t nw = (blockDim.x + 63) >> 6;
-        for (int32_t w = 1; w < nw; ++w) {
+        for (int32_t w = 1; w < 4; ++w) {
             mnx = min(mnx, red[w][0]);
             mny = min(mny, red[w][1]);
             mxx = max(mxx, red[w][2]);
             mxy = max(mxy, red[w][3]);
         }
-        atomicMin(&bbox[4 * s0 + 0], mnx);
-        atomicMin(&bbox[4 * s0 + 1], mny);
-        atomicMax(&bbox[4 * s0 + 2], mxx);
-        atomicMax(&bbox[4 * s0 + 3], mxy);
+        const int32_t s = ch.x;
+        atomicMin(&bbox[4 * s + 0], mnx);
+        atomicMin(&bbox[4 * s + 1], mny);
+        atomicMax(&bbox[4 * s + 2], mxx);
+        atomicMax(&bbox[4 * s + 3], mxy);
     }
 }
 
@@ -449,209 +440,15 @@ __global__ __launch_bounds__(256) void k_knn(const float4 *__restrict__ sorted,
     ncount[s] = cnt;
 }
 
-// ------------------------------------------------------------------ half-planes
+}  // namespace orca
 
-// Shortest change u of the relative velocity V = v_i - v_j out of the velocity
-// obstacle of neighbour j (relative position P = x_j - x_i, combined radius R,
-// look-ahead tau) and the outward normal n at V + u (Fig. 1(b)-(c)).  A pair
-// already closer than R uses the one-step disc D(P/dt, R/dt).  No fused
-// multiply-add: the operations are rounded one by one.
-__device__ __forceinline__ void obstacle_exit(double Px, double Py, double Vx, double Vy, double R,
-                                              double tau, double dt, bool i_first, double &ux,
-                                              double &uy, double &nx, double &ny)
-{
-#pragma clang fp contract(off)
-    const double dist2 = Px * Px + Py * Py;
-    const double R2 = R * R;
-    if (dist2 > R2) {
-        const double wx = Vx - Px / tau, wy = Vy - Py / tau;
-        const double w2 = wx * wx + wy * wy;
-        const double wP = wx * Px + wy * Py;
-        if (wP < 0.0 && wP * wP > R2 * w2) {
-            // V faces the cut-off arc
-            const double wl = sqrt(w2);
-            nx = wx / wl;
-            ny = wy / wl;
-            const double f = R / tau - wl;
-            ux = f * nx;
-            uy = f * ny;
-            return;
-        }
-        // nearest boundary point on a tangent leg; left if V is left of P
-        const double L = sqrt(dist2 - R2);
-        double lx, ly;
-        if (Px * wy - Py * wx > 0.0) {
-            lx = (Px * L - Py * R) / dist2;
-            ly = (Px * R + Py * L) / dist2;
-            nx = -ly;
-            ny = lx;
-        } else {
-            lx = (Px * L + Py * R) / dist2;
-            ly = (-Px * R + Py * L) / dist2;
-            nx = ly;
-            ny = -lx;
-        }
-        const double sdot = Vx * lx + Vy * ly;
-        ux = sdot * lx - Vx;
-        uy = sdot * ly - Vy;
-        return;
-    }
-    const double wx = Vx - Px / dt, wy = Vy - Py / dt;
-    const double wl = sqrt(wx * wx + wy * wy);
-    if (wl > 0.0) {
-        nx = wx / wl;
-        ny = wy / wl;
-    } else if (dist2 > 0.0) {
-        const double pl = sqrt(dist2);
-        nx = -Px / pl;
-        ny = -Py / pl;
-    } else {
-        nx = i_first ? 1.0 : -1.0;
-        ny = 0.0;
-    }
-    const double f = R / dt - wl;
-    ux = f * nx;
-    uy = f * ny;
-}
+#include "orca_lp.h"
 
-// Constraint store of one lane: element k at [k * kLpBlock + lane] of the
-// block's LDS arrays.  Half-plane k is {v : n_k . v >= b_k}.
-struct Lane {
-    double *nx, *ny, *b;
-    __device__ __forceinline__ double NX(int k) const { return nx[k * kLpBlock]; }
-    __device__ __forceinline__ double NY(int k) const { return ny[k * kLpBlock]; }
-    __device__ __forceinline__ double B(int k) const { return b[k * kLpBlock]; }
-};
+namespace orca {
 
-// Incremental 2D LP: the point of the disc |v| <= vmax and of the half-planes
-// n_k.v >= b_k - relax closest to vhat.  Constraints enter one by one; when
-// the current point violates constraint k the new optimum lies on its line,
-// found by a 1D program against the disc and constraints 0..k-1.  Returns -1
-// (feasible, v set) or the first k whose 1D program is empty (v = the optimum
-// over constraints 0..k-1).
-__device__ int lp2_project(const Lane &L, int m, double relax, double vmax, double vhx, double vhy,
-                           double &vx, double &vy)
-{
-    const double vm2 = vmax * vmax;
-    const double vh2 = vhx * vhx + vhy * vhy;
-    if (vh2 > vm2) {
-        const double sc = vmax / sqrt(vh2);
-        vx = vhx * sc;
-        vy = vhy * sc;
-    } else {
-        vx = vhx;
-        vy = vhy;
-    }
-    for (int k = 0; k < m; ++k) {
-        const double nkx = L.NX(k), nky = L.NY(k), bk = L.B(k) - relax;
-        if (nkx * vx + nky * vy >= bk) continue;
-        double h2 = vm2 - bk * bk;
-        if (h2 < 0.0) {
-            if (bk > 0.0) return k;  // the line misses the disc on the far side
-            h2 = 0.0;
-        }
-        const double h = sqrt(h2);
-        double lo = -h, hi = h;
-        // line k: p(t) = bk n_k + t d_k with d_k = (-nky, nkx)
-        for (int j = 0; j < k; ++j) {
-            const double njx = L.NX(j), njy = L.NY(j), bj = L.B(j) - relax;
-            const double den = njy * nkx - njx * nky;           // n_j . d_k
-            const double num = bj - bk * (njx * nkx + njy * nky); // b_j - n_j . (bk n_k)
-            if (den > 0.0) lo = fmax(lo, num / den);
-            else if (den < 0.0) hi = fmin(hi, num / den);
-            else if (num > 0.0) return k;
-        }
-        if (lo > hi) return k;
-        const double t = fmin(fmax(nkx * vhy - nky * vhx, lo), hi);  // d_k . vhat, clamped
-        vx = bk * nkx - t * nky;
-        vy = bk * nky + t * nkx;
-    }
-    return -1;
-}
-
-// Projected constraint i of the plane-k subproblem: i = -1 is "no negative
-// penetration" (-n_k . v >= -b_k), i >= 0 is "constraint i penetrates no more
-// than k" ((n_i - n_k) . v >= b_i - b_k).
-__device__ __forceinline__ void plane_row(const Lane &L, int i, double nkx, double nky, double bk,
-                                          double &mx, double &my, double &c)
-{
-    if (i < 0) {
-        mx = -nkx;
-        my = -nky;
-        c = -bk;
-    } else {
-        mx = L.NX(i) - nkx;
-        my = L.NY(i) - nky;
-        c = L.B(i) - bk;
-    }
-}
-
-// Maximise n_k . v over the disc and the projected constraints -1..k-1
-// (incremental, as lp2_project but with a linear objective).  Returns false
-// if the subproblem is empty.
-__device__ bool lp2_plane(const Lane &L, int k, double nkx, double nky, double bk, double vmax,
-                          double &vx, double &vy)
-{
-    const double vm2 = vmax * vmax;
-    vx = vmax * nkx;
-    vy = vmax * nky;
-    for (int i = -1; i < k; ++i) {
-        double mx, my, ci;
-        plane_row(L, i, nkx, nky, bk, mx, my, ci);
-        if (mx * vx + my * vy >= ci) continue;
-        const double mm = mx * mx + my * my;
-        if (mm == 0.0) {
-            if (ci > 0.0) return false;
-            continue;
-        }
-        const double disc = vm2 * mm - ci * ci;
-        if (disc < 0.0) return false;
-        const double hs = sqrt(disc) / mm;
-        double lo = -hs, hi = hs;
-        const double p0x = ci * mx / mm, p0y = ci * my / mm;
-        // line i: p(s) = p0 + s (-my, mx)
-        for (int j = -1; j < i; ++j) {
-            double ax, ay, cj;
-            plane_row(L, j, nkx, nky, bk, ax, ay, cj);
-            const double den = ay * mx - ax * my;
-            const double num = cj - (ax * p0x + ay * p0y);
-            if (den > 0.0) lo = fmax(lo, num / den);
-            else if (den < 0.0) hi = fmin(hi, num / den);
-            else if (num > 0.0) return false;
-        }
-        if (lo > hi) return false;
-        const double slope = nky * mx - nkx * my;  // n_k . (-my, mx)
-        const double sbest = slope > 0.0 ? hi : (slope < 0.0 ? lo : fmin(fmax(0.0, lo), hi));
-        vx = p0x - sbest * my;
-        vy = p0y + sbest * mx;
-    }
-    return true;
-}
-
-// Least penetration d* = min over the disc of max_k (b_k - n_k . v), by an
-// incremental 3D program in (v, t) with t >= 0, starting from a point that
-// satisfies constraints 0..start-1 (so t = 0 is optimal for them).  When
-// constraint k is violated beyond the current t, the new optimum has
-// t = b_k - n_k . v: maximise n_k . v on that plane.
-__device__ double lp3_least_penetration(const Lane &L, int m, int start, double vmax, double &vx,
-                                        double &vy)
-{
-    double t = 0.0;
-    for (int k = start; k < m; ++k) {
-        const double nkx = L.NX(k), nky = L.NY(k), bk = L.B(k);
-        if (nkx * vx + nky * vy + t >= bk) continue;
-        double wx, wy;
-        if (lp2_plane(L, k, nkx, nky, bk, vmax, wx, wy)) {
-            vx = wx;
-            vy = wy;
-            t = fmax(bk - (nkx * vx + nky * vy), 0.0);
-        }
-    }
-    return t;
-}
+static_assert(kLpStride == kLpBlock, "LP constraint stride must equal the LP block size");
 
 // Load agent s's neighbours, build the half-planes into the lane's LDS column.
-template <int KMAX>
 __device__ __forceinline__ int build_constraints(const Lane &L, int32_t s, int32_t id, float4 me,
                                                  const SceneDev &p, const float4 *__restrict__ sorted,
                                                  const int32_t *__restrict__ inv,
@@ -671,8 +468,7 @@ __device__ __forceinline__ int build_constraints(const Lane &L, int32_t s, int32
         double ux, uy, nx, ny;
         obstacle_exit(Px, Py, Vx, Vy, R, tau, dt, id < jid, ux, uy, nx, ny);
         const double qx = vix + 0.5 * ux, qy = viy + 0.5 * uy;
-        L.nx[k * kLpBlock] = nx;
-        L.ny[k * kLpBlock] = ny;
+        L.n[k * kLpBlock] = make_double2(nx, ny);
         L.b[k * kLpBlock] = nx * qx + ny * qy;
         if (nbr_out) nbr_out[(int64_t)id * krow + k] = jid;
     }
@@ -729,8 +525,10 @@ __device__ __forceinline__ void write_result(const OutArgs &o, const SceneDev &p
     if (o.status) o.status[id] = status;
 }
 
-// One lane per agent in cell order.  Feasible agents finish here; agents whose
-// 2D program is empty are appended to the fallback list (one atomic per wave).
+// One lane per agent in cell order.  Feasible agents finish here; an agent
+// whose 2D program is empty is appended to the fallback list with the index
+// where it failed and the optimum of the constraints before it (one atomic
+// per wave).
 template <int KMAX>
 __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sorted,
                                                  const int32_t *__restrict__ sid,
@@ -739,27 +537,35 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
                                                  const SceneDev *__restrict__ sp, int32_t n,
                                                  const int32_t *__restrict__ nbr, int32_t ld,
                                                  const int32_t *__restrict__ ncount,
-                                                 OutArgs out, int32_t *__restrict__ fb_list,
+                                                 OutArgs out, FallbackItem *__restrict__ fb_list,
                                                  Counters *__restrict__ counters)
 {
-    __shared__ double s_nx[KMAX * kLpBlock];
-    __shared__ double s_ny[KMAX * kLpBlock];
+    __shared__ double2 s_n[KMAX * kLpBlock];
     __shared__ double s_b[KMAX * kLpBlock];
     const int32_t s = blockIdx.x * kLpBlock + threadIdx.x;
     bool need_fb = false;
+    FallbackItem item;
     if (s < n) {
-        const Lane L{s_nx + threadIdx.x, s_ny + threadIdx.x, s_b + threadIdx.x};
+        const Lane L{s_n + threadIdx.x, s_b + threadIdx.x};
         const float4 me = sorted[s];
         const int32_t id = sid[s];
         const SceneDev p = sp[agent_scene[id]];
         double vhx, vhy;
         preferred_velocity(p, me, id, n, out.pref, out.goals, vhx, vhy);
-        const int m = build_constraints<KMAX>(L, s, id, me, p, sorted, inv, nbr, ld, ncount,
-                                              out.nbr_out, out.krow);
+        const int m = build_constraints(L, s, id, me, p, sorted, inv, nbr, ld, ncount,
+                                        out.nbr_out, out.krow);
         double vx, vy;
-        const int fail = lp2_project(L, m, 0.0, (double)p.vmax, vhx, vhy, vx, vy);
-        if (fail < 0) write_result(out, p, me, id, n, vx, vy, vhx, vhy, 0);
-        else need_fb = true;
+        disc_clip((double)p.vmax, vhx, vhy, vx, vy);
+        const int fail = lp2_project(L, m, 0, 0.0, (double)p.vmax, vhx, vhy, vx, vy);
+        if (fail < 0) {
+            write_result(out, p, me, id, n, vx, vy, vhx, vhy, 0);
+        } else {
+            need_fb = true;
+            item.s = s;
+            item.fail = fail;
+            item.vx = vx;
+            item.vy = vy;
+        }
     }
     const uint64_t mask = __ballot(need_fb);
     if (mask) {
@@ -770,13 +576,13 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
         const int leader = __ffsll((unsigned long long)mask) - 1;
         if ((int)lane == leader) slot0 = atomicAdd(&counters->n_fallback, (uint32_t)__popcll(mask));
         slot0 = __shfl(slot0, leader, 64);
-        if (need_fb) fb_list[slot0 + before] = s;
+        if (need_fb) fb_list[slot0 + before] = item;
     }
 }
 
-// Persistent over the fallback list: rebuild the half-planes, rerun the 2D
-// program to its first empty step, find the least penetration d*, then take
-// the point closest to vhat among those within d* + delta of every half-plane.
+// Persistent over the fallback list: rebuild the half-planes, find the least
+// penetration d* from the 2D program's last optimum, then take the point
+// closest to vhat among those within d* + delta of every half-plane.
 template <int KMAX>
 __global__ __launch_bounds__(kLpBlock) void k_fallback(const float4 *__restrict__ sorted,
                                                        const int32_t *__restrict__ sid,
@@ -787,38 +593,33 @@ __global__ __launch_bounds__(kLpBlock) void k_fallback(const float4 *__restrict_
                                                        int32_t ld,
                                                        const int32_t *__restrict__ ncount,
                                                        OutArgs out,
-                                                       const int32_t *__restrict__ fb_list,
+                                                       const FallbackItem *__restrict__ fb_list,
                                                        const Counters *__restrict__ counters)
 {
-    __shared__ double s_nx[KMAX * kLpBlock];
-    __shared__ double s_ny[KMAX * kLpBlock];
+    __shared__ double2 s_n[KMAX * kLpBlock];
     __shared__ double s_b[KMAX * kLpBlock];
     const uint32_t count = counters->n_fallback;
-    const Lane L{s_nx + threadIdx.x, s_ny + threadIdx.x, s_b + threadIdx.x};
+    const Lane L{s_n + threadIdx.x, s_b + threadIdx.x};
     for (uint32_t idx = blockIdx.x * kLpBlock + threadIdx.x; idx < count;
          idx += gridDim.x * kLpBlock) {
-        const int32_t s = fb_list[idx];
+        const FallbackItem item = fb_list[idx];
+        const int32_t s = item.s;
         const float4 me = sorted[s];
         const int32_t id = sid[s];
         const SceneDev p = sp[agent_scene[id]];
         double vhx, vhy;
         preferred_velocity(p, me, id, n, out.pref, out.goals, vhx, vhy);
-        const int m = build_constraints<KMAX>(L, s, id, me, p, sorted, inv, nbr, ld, ncount,
-                                              nullptr, 0);
+        const int m = build_constraints(L, s, id, me, p, sorted, inv, nbr, ld, ncount, nullptr, 0);
         const double vmax = (double)p.vmax;
-        double vx, vy;
-        const int fail = lp2_project(L, m, 0.0, vmax, vhx, vhy, vx, vy);
-        uint8_t status = 0;
-        if (fail >= 0) {
-            status = 1;
-            const double d = lp3_least_penetration(L, m, fail, vmax, vx, vy);
-            double wx, wy;
-            if (lp2_project(L, m, d + kDelta, vmax, vhx, vhy, wx, wy) < 0) {
-                vx = wx;
-                vy = wy;
-            }
+        double vx = item.vx, vy = item.vy;
+        const double d = lp3_least_penetration(L, m, item.fail, vmax, vx, vy);
+        double wx, wy;
+        disc_clip(vmax, vhx, vhy, wx, wy);
+        if (lp2_project(L, m, 0, d + kDelta, vmax, vhx, vhy, wx, wy) < 0) {
+            vx = wx;
+            vy = wy;
         }
-        write_result(out, p, me, id, n, vx, vy, vhx, vhy, status);
+        write_result(out, p, me, id, n, vx, vy, vhx, vhy, 1);
     }
 }
 
@@ -886,8 +687,8 @@ hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, hipSt
 {
     const int32_t n = pl.n;
     if (n > 0)
-        hipLaunchKernelGGL(k_bbox, dim3((n + 255) / 256), dim3(256), 0, st, pos, n,
-                           pl.agent_scene, pl.bbox);
+        hipLaunchKernelGGL(k_bbox, dim3(pl.n_chunks), dim3(256), 0, st, pos, n, pl.chunks,
+                           pl.off, pl.bbox);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, pl.n_scenes, pl.off, pl.sp, pl.bbox,
                        pl.grid, pl.counters, pl.max_cells);
     if (n == 0) return hipGetLastError();

@@ -1,0 +1,296 @@
+// orca_lp.h -- per-agent geometry and linear programs of the ORCA step
+// (float64), used by the velocity kernels.
+//
+//   obstacle_exit          Fig. 1(b)-(c): shortest exit u from the velocity
+//                          obstacle and the outward normal
+//   lp2_project            section 3: permitted velocity closest to the
+//                          preferred one (incremental 2D program)
+//   lp3_least_penetration  section 3, infeasible case: least penetration d*
+//                          (incremental 3D program on the plane of each
+//                          violated constraint)
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define ORCA_HD __host__ __device__
+#else
+#define ORCA_HD
+struct double2 {
+    double x, y;
+};
+inline double2 make_double2(double x, double y) { return double2{x, y}; }
+#endif
+
+namespace orca {
+
+#ifndef ORCA_LP_STRIDE
+constexpr int kLpStride = 64;  // lanes per LP block: element k of a lane at [k * kLpStride]
+#else
+constexpr int kLpStride = ORCA_LP_STRIDE;
+#endif
+
+// Shortest change u of the relative velocity V = v_i - v_j out of the velocity
+// obstacle of neighbour j (relative position P = x_j - x_i, combined radius R,
+// look-ahead tau) and the outward normal n at V + u (Fig. 1(b)-(c)).  A pair
+// already closer than R uses the one-step disc D(P/dt, R/dt).  No fused
+// multiply-add: the operations are rounded one by one.
+ORCA_HD inline void obstacle_exit(double Px, double Py, double Vx, double Vy, double R,
+                                              double tau, double dt, bool i_first, double &ux,
+                                              double &uy, double &nx, double &ny)
+{
+#pragma clang fp contract(off)
+    const double dist2 = Px * Px + Py * Py;
+    const double R2 = R * R;
+    if (dist2 > R2) {
+        const double wx = Vx - Px / tau, wy = Vy - Py / tau;
+        const double w2 = wx * wx + wy * wy;
+        const double wP = wx * Px + wy * Py;
+        if (wP < 0.0 && wP * wP > R2 * w2) {
+            // V faces the cut-off arc
+            const double wl = sqrt(w2);
+            nx = wx / wl;
+            ny = wy / wl;
+            const double f = R / tau - wl;
+            ux = f * nx;
+            uy = f * ny;
+            return;
+        }
+        // nearest boundary point on a tangent leg; left if V is left of P
+        const double L = sqrt(dist2 - R2);
+        double lx, ly;
+        if (Px * wy - Py * wx > 0.0) {
+            lx = (Px * L - Py * R) / dist2;
+            ly = (Px * R + Py * L) / dist2;
+            nx = -ly;
+            ny = lx;
+        } else {
+            lx = (Px * L + Py * R) / dist2;
+            ly = (-Px * R + Py * L) / dist2;
+            nx = ly;
+            ny = -lx;
+        }
+        const double sdot = Vx * lx + Vy * ly;
+        ux = sdot * lx - Vx;
+        uy = sdot * ly - Vy;
+        return;
+    }
+    const double wx = Vx - Px / dt, wy = Vy - Py / dt;
+    const double wl = sqrt(wx * wx + wy * wy);
+    if (wl > 0.0) {
+        nx = wx / wl;
+        ny = wy / wl;
+    } else if (dist2 > 0.0) {
+        const double pl = sqrt(dist2);
+        nx = -Px / pl;
+        ny = -Py / pl;
+    } else {
+        nx = i_first ? 1.0 : -1.0;
+        ny = 0.0;
+    }
+    const double f = R / dt - wl;
+    ux = f * nx;
+    uy = f * ny;
+}
+
+// Constraint store of one lane in the block's LDS: half-plane k is
+// {v : n_k . v >= b_k}; n_k is one 16-byte double2 at [k * kLpStride + lane],
+// b_k a double at the same index of a second array.
+struct Lane {
+    double2 *n;
+    double *b;
+    ORCA_HD inline double2 N(int k) const { return n[k * kLpStride]; }
+    ORCA_HD inline double B(int k) const { return b[k * kLpStride]; }
+};
+
+// Feasible interval lo <= s <= hi of a 1D program, each end kept as a
+// fraction with a positive denominator and compared by cross-multiplication,
+// so adding a constraint costs no division.
+struct Interval {
+    double lo_n, lo_d, hi_n, hi_d;
+    bool bad;
+    ORCA_HD inline void init(double h_n, double h_d)
+    {
+        lo_n = -h_n;
+        lo_d = h_d;
+        hi_n = h_n;
+        hi_d = h_d;
+        bad = false;
+    }
+    // add s * den >= num
+    ORCA_HD inline void add(double den, double num)
+    {
+        const bool up = den > 0.0, down = den < 0.0;
+        const bool raise = up && num * lo_d > lo_n * den;
+        const bool lower = down && num * hi_d > hi_n * den;  // num/den < hi, den < 0
+        lo_n = raise ? num : lo_n;
+        lo_d = raise ? den : lo_d;
+        hi_n = lower ? -num : hi_n;
+        hi_d = lower ? -den : hi_d;
+        bad = bad || (!up && !down && num > 0.0);
+    }
+    ORCA_HD inline bool empty() const { return bad || lo_n * hi_d > hi_n * lo_d; }
+    // t clamped into the interval, as a fraction (t_n / t_d)
+    ORCA_HD inline void clamp(double t, double &t_n, double &t_d) const
+    {
+        if (t * lo_d < lo_n) {
+            t_n = lo_n;
+            t_d = lo_d;
+        } else if (t * hi_d > hi_n) {
+            t_n = hi_n;
+            t_d = hi_d;
+        } else {
+            t_n = t;
+            t_d = 1.0;
+        }
+    }
+};
+
+// Incremental 2D LP: the point of the disc |v| <= vmax and of the half-planes
+// n_k.v >= b_k - relax closest to vhat, constraints taken from index `from`
+// on with (vx, vy) optimal for the ones before.  When the current point
+// violates constraint k the new optimum lies on its line, found by a 1D
+// program against the disc and constraints 0..k-1.  Returns -1 (feasible, v
+// set) or the first k whose 1D program is empty (v = the optimum over
+// constraints 0..k-1).
+ORCA_HD inline int lp2_project(const Lane &L, int m, int from, double relax, double vmax, double vhx,
+                           double vhy, double &vx, double &vy)
+{
+    const double vm2 = vmax * vmax;
+    for (int k = from; k < m; ++k) {
+        const double2 nk = L.N(k);
+        const double bk = L.B(k) - relax;
+        if (nk.x * vx + nk.y * vy >= bk) continue;
+        double h2 = vm2 - bk * bk;
+        if (h2 < 0.0) {
+            if (bk > 0.0) return k;  // the line misses the disc on the far side
+            h2 = 0.0;
+        }
+        // line k: p(t) = bk n_k + t d_k with d_k = (-n_k.y, n_k.x)
+        Interval iv;
+        iv.init(sqrt(h2), 1.0);
+        for (int j = 0; j < k; ++j) {
+            const double2 nj = L.N(j);
+            const double bj = L.B(j) - relax;
+            iv.add(nj.y * nk.x - nj.x * nk.y, bj - bk * (nj.x * nk.x + nj.y * nk.y));
+        }
+        if (iv.empty()) return k;
+        double tn, td;
+        iv.clamp(nk.x * vhy - nk.y * vhx, tn, td);  // d_k . vhat, clamped
+        const double t = tn / td;
+        vx = bk * nk.x - t * nk.y;
+        vy = bk * nk.y + t * nk.x;
+    }
+    return -1;
+}
+
+// Start of lp2_project: vhat, pulled radially into the disc.
+ORCA_HD inline void disc_clip(double vmax, double vhx, double vhy, double &vx,
+                                          double &vy)
+{
+    const double vh2 = vhx * vhx + vhy * vhy;
+    if (vh2 > vmax * vmax) {
+        const double sc = vmax / sqrt(vh2);
+        vx = vhx * sc;
+        vy = vhy * sc;
+    } else {
+        vx = vhx;
+        vy = vhy;
+    }
+}
+
+// Projected constraint i of the plane-k subproblem: i = -1 is "no negative
+// penetration" (-n_k . v >= -b_k), i >= 0 is "constraint i penetrates no more
+// than k" ((n_i - n_k) . v >= b_i - b_k).
+ORCA_HD inline void plane_row(const Lane &L, int i, double2 nk, double bk, double &mx,
+                                          double &my, double &c)
+{
+    if (i < 0) {
+        mx = -nk.x;
+        my = -nk.y;
+        c = -bk;
+    } else {
+        const double2 ni = L.N(i);
+        mx = ni.x - nk.x;
+        my = ni.y - nk.y;
+        c = L.B(i) - bk;
+    }
+}
+
+// Maximise n_k . v over the disc and the projected constraints -1..k-1
+// (incremental, as lp2_project but with a linear objective).  Line i is
+// p(s) = c_i m_i / |m_i|^2 + s (-m_i.y, m_i.x); each constraint j on it is
+// multiplied through by |m_i|^2 > 0 so no division is needed until the end.
+// Returns false if the subproblem is empty.
+ORCA_HD inline bool lp2_plane(const Lane &L, int k, double2 nk, double bk, double vmax, double &vx,
+                          double &vy)
+{
+    const double vm2 = vmax * vmax;
+    vx = vmax * nk.x;
+    vy = vmax * nk.y;
+    for (int i = -1; i < k; ++i) {
+        double mx, my, ci;
+        plane_row(L, i, nk, bk, mx, my, ci);
+        if (mx * vx + my * vy >= ci) continue;
+        const double mm = mx * mx + my * my;
+        if (mm == 0.0) {
+            if (ci > 0.0) return false;
+            continue;
+        }
+        const double disc = vm2 * mm - ci * ci;
+        if (disc < 0.0) return false;
+        // s in [-sqrt(disc), sqrt(disc)] / mm
+        Interval iv;
+        iv.init(sqrt(disc), mm);
+        for (int j = -1; j < i; ++j) {
+            double ax, ay, cj;
+            plane_row(L, j, nk, bk, ax, ay, cj);
+            // a.(c_i m / mm + s d) >= c_j  ->  s (a.d) mm >= c_j mm - c_i (a.m)
+            iv.add((ay * mx - ax * my) * mm, cj * mm - ci * (ax * mx + ay * my));
+        }
+        if (iv.empty()) return false;
+        const double slope = nk.y * mx - nk.x * my;  // n_k . (-my, mx)
+        double sn, sd;
+        if (slope > 0.0) {
+            sn = iv.hi_n;
+            sd = iv.hi_d;
+        } else if (slope < 0.0) {
+            sn = iv.lo_n;
+            sd = iv.lo_d;
+        } else {
+            iv.clamp(0.0, sn, sd);
+        }
+        const double s = sn / sd;
+        const double c0 = ci / mm;
+        vx = c0 * mx - s * my;
+        vy = c0 * my + s * mx;
+    }
+    return true;
+}
+
+// Least penetration d* = min over the disc of max_k (b_k - n_k . v), by an
+// incremental 3D program in (v, t) with t >= 0, starting from a point that
+// satisfies constraints 0..start-1 (so t = 0 is optimal for them).  When
+// constraint k is violated beyond the current t, the new optimum has
+// t = b_k - n_k . v: maximise n_k . v on that plane.
+ORCA_HD inline double lp3_least_penetration(const Lane &L, int m, int start, double vmax, double &vx,
+                                        double &vy)
+{
+    double t = 0.0;
+    for (int k = start; k < m; ++k) {
+        const double2 nk = L.N(k);
+        const double bk = L.B(k);
+        if (nk.x * vx + nk.y * vy + t >= bk) continue;
+        double wx, wy;
+        if (lp2_plane(L, k, nk, bk, vmax, wx, wy)) {
+            vx = wx;
+            vy = wy;
+            t = fmax(bk - (nk.x * vx + nk.y * vy), 0.0);
+        }
+    }
+    return t;
+}
+
+}  // namespace orca
