@@ -73,6 +73,55 @@ def cpu_baseline(w, sample: int):
                        "agents included), %.1f s" % (len(agents), w.n, dt))
 
 
+def batched_forms(steps: int, no_autotune: bool):
+    """512 independent scenes: one graph-replayed launch sequence per step over
+    all scenes, against stepping each scene with its own plain orca_step."""
+    import torch
+    from paper_1908_10107_amd import orca, scenes
+    w = scenes.batched()
+    kmax = max(p.max_neighbors for p in w.params)
+    d = orca.to_device(w)
+    ctx = orca.Context(max_agents=w.n, max_scenes=w.n_scenes, k_max=kmax)
+    tuned = None
+    if not no_autotune:
+        ctx.build_grid(w.offsets, w.params, d["pos"])
+        tuned = ctx.autotune(d["pos"], d["vel"], d["pref_vel"], goals=d["goals"], reps=2)
+    ctx.step_graph(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], goals=d["goals"],
+                   n_steps=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step_graph(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], goals=d["goals"],
+                   n_steps=steps)
+    torch.cuda.synchronize()
+    gw = time.perf_counter() - t0
+    ctx.close()
+    # per-scene plain forward, one context per scene (no re-uploads between calls)
+    per = []
+    for s in range(w.n_scenes):
+        one = w.subset_scenes([s])
+        c = orca.Context(max_agents=max(one.n, 1), max_scenes=1, k_max=kmax)
+        per.append((one, c, orca.to_device(one)))
+    for one, c, t in per:
+        c.step(one.offsets, one.params, t["pos"], t["vel"], t["pref_vel"], goals=t["goals"])
+    torch.cuda.synchronize()
+    ps = max(2, steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(ps):
+        for one, c, t in per:
+            c.step(one.offsets, one.params, t["pos"], t["vel"], t["pref_vel"], goals=t["goals"])
+    torch.cuda.synchronize()
+    pw = time.perf_counter() - t0
+    for _, c, _ in per:
+        c.close()
+    bg = w.n * steps / gw
+    bp = w.n * ps / pw
+    return {"batched_graph": {"value": bg, "ms_per_step": 1e3 * gw / steps, "agents": w.n,
+                              "scenes": w.n_scenes, "steps": steps,
+                              "autotune": None if tuned is None else list(tuned)},
+            "batched_per_scene_plain": {"value": bp, "ms_per_step": 1e3 * pw / ps, "steps": ps},
+            "batched_speedup": bg / bp}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +131,14 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=262144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="plain,batched",
+                    help="comma list: plain (always), batched (512 scenes, graph replay vs "
+                         "per-scene plain steps)")
+    ap.add_argument("--batched-steps", type=int, default=20)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one elementwise copy of 256 MiB (reads and writes known bytes) "
+                         "to scale hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -100,6 +157,10 @@ def main():
     st = dict(pos=base["pos"].clone(), vel=base["vel"].clone(), pref=base["pref_vel"].clone())
     step = lambda k: ctx.step(w.offsets, w.params, st["pos"], st["vel"], st["pref"],
                               goals=base["goals"], n_steps=k)
+    tuned = None
+    if not args.no_autotune:
+        ctx.build_grid(w.offsets, w.params, st["pos"])
+        tuned = ctx.autotune(st["pos"], st["vel"], st["pref"], goals=base["goals"], reps=2)
     if args.warmup:
         step(args.warmup)
     torch.cuda.synchronize()
@@ -135,6 +196,28 @@ def main():
                                                           ("k_knn" if dom == 1 else "binning")),
                     stage_ms=stages, fallback_agents_per_step=round(fb_avg, 1))
 
+    # the same plain step replayed from a captured graph (launch cost only differs)
+    gstep = lambda k: ctx.step_graph(w.offsets, w.params, st["pos"], st["vel"], st["pref"],
+                                     goals=base["goals"], n_steps=k)
+    gstep(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gstep(args.steps)
+    torch.cuda.synchronize()
+    gwall = time.perf_counter() - t0
+    forms = {"plain_graph": {"value": w.n * args.steps / gwall,
+                             "ms_per_step": 1e3 * gwall / args.steps}}
+    ctx.close()
+    del st, base
+    if "batched" in args.forms.split(","):
+        forms.update(batched_forms(args.batched_steps, args.no_autotune))
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = src * 1.0
+        torch.cuda.synchronize()
+        del src, dst
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_sample)
@@ -150,9 +233,11 @@ def main():
                    "state": "f32", "lp": "f64", "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "autotune": None if tuned is None else {"knn_block": tuned[0],
+                                                "fallback_waves_per_cu": tuned[1]},
+        "forms": forms,
     }
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -154,6 +154,31 @@ int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
               const float *goals, int32_t n_steps, int32_t save_tape);
 
 /*
+ * orca_step for many steps at the lowest launch cost: the first call captures
+ * one whole step (every kernel of every scene; no host synchronisation and no
+ * memory set nodes inside) into a HIP graph on a private capture stream, and
+ * every step replays that graph on the context stream.  The graph is captured
+ * again when pos / vel / pref_vel / goals, the scene set or the launch shapes
+ * change.  The first call waits for the context stream once.  Not available
+ * while profiling is on (ESTATE).  No tape is recorded.
+ */
+int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
+                    const orca_params *params, float *pos, float *vel, float *pref_vel,
+                    const float *goals, int32_t n_steps);
+
+/*
+ * Pick the launch shapes for the current workload: threads per neighbour
+ * block (64, 128, 256, 512) and persistent fallback waves per compute unit
+ * (4, 8, 16, 32, i.e. how many fallback agents each lane takes on), by timing
+ * reps velocity passes per candidate with HIP events.  Needs orca_build_grid
+ * on pos first; writes only new_vel (device [2, N], scratch).  The choice is
+ * kept in the context and returned in choice[2] (nullable).  Waits for the
+ * stream.
+ */
+int orca_autotune(orca_ctx *ctx, const float *pos, const float *vel, const float *pref_vel,
+                  const float *goals, float *new_vel, int32_t reps, int32_t *choice);
+
+/*
  * Vector-Jacobian product of recorded step tape_step (0-based, of the last
  * orca_step call with save_tape = 1; no goals).  Given the gradients of a loss
  * with respect to the state after the step (g_pos_next, g_vel_next, device

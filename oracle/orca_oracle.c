@@ -36,6 +36,7 @@
  * leaves open; no printed number fixes them ("parity unpinned" for those two
  * choices, pinned only by the invariants they satisfy).
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -59,9 +60,6 @@ typedef struct {
     int32_t max_neighbors, pad;
 } oracle_params;
 
-typedef struct {
-    double qx, qy, nx, ny;
-} halfplane;
 
 /* Threads the parallel loops use. */
 int oracle_threads(void)
@@ -223,219 +221,50 @@ void oracle_knn_binned_scene(int64_t n_total, const float *pos, int64_t lo, int6
 }
 
 /* ------------------------------------------------------------------ */
-/* Half-plane of one neighbour (Fig. 1)                                */
+/* Geometry and programs: the core, once in double, once complex-step  */
 /* ------------------------------------------------------------------ */
 
-/*
- * P = x_j - x_i, V = v_i - v_j, R = r_i + r_j.  The velocity obstacle for
- * look-ahead tau is the set of relative velocities that bring the pair closer
- * than R at some t in (0, tau]: a cone from the origin tangent to the disc
- * D(P, R), cut off by the disc D(P/tau, R/tau).  u runs from V to the closest
- * boundary point and n is the outward normal there.  Pairs already closer
- * than R use dt in place of tau (they must separate within one step).
- * Returns the branch code.
- */
+#define REAL double
+#define FN(x) x
+#define RE(x) (x)
+#define SQRT(x) sqrt(x)
+#include "orca_oracle_core.h"
+#undef REAL
+#undef FN
+#undef RE
+#undef SQRT
+
+#define REAL double complex
+#define FN(x) x##_cx
+#define RE(x) creal(x)
+#define SQRT(x) csqrt(x)
+#include "orca_oracle_core.h"
+#undef REAL
+#undef FN
+#undef RE
+#undef SQRT
+
+typedef halfplane_t halfplane;
+
+/* Half-plane of one neighbour; see obstacle() in orca_oracle_core.h. */
 int oracle_halfplane(double Px, double Py, double Vx, double Vy, double R, double tau,
                      double dt, int i_before_j, double *ux, double *uy, double *nx,
                      double *ny)
 {
-    double dist2 = Px * Px + Py * Py;
-    double R2 = R * R;
-    if (dist2 > R2) {
-        /* w: from the centre of the cut-off disc to V */
-        double wx = Vx - Px / tau, wy = Vy - Py / tau;
-        double w2 = wx * wx + wy * wy;
-        double wP = wx * Px + wy * Py;
-        if (wP < 0.0 && wP * wP > R2 * w2) {
-            /* V faces the cut-off arc: nearest boundary point is on the circle */
-            double wl = sqrt(w2);
-            *nx = wx / wl;
-            *ny = wy / wl;
-            *ux = (R / tau - wl) * *nx;
-            *uy = (R / tau - wl) * *ny;
-            return ORC_ARC;
-        }
-        /* otherwise the nearest boundary point is on one of the two tangent legs */
-        double L = sqrt(dist2 - R2);
-        double lx, ly;
-        int code;
-        if (Px * wy - Py * wx > 0.0) {
-            /* left leg: P's direction turned counter-clockwise by asin(R/|P|) */
-            lx = (Px * L - Py * R) / dist2;
-            ly = (Px * R + Py * L) / dist2;
-            *nx = -ly;
-            *ny = lx;
-            code = ORC_LEFT;
-        } else {
-            /* right leg: turned clockwise */
-            lx = (Px * L + Py * R) / dist2;
-            ly = (-Px * R + Py * L) / dist2;
-            *nx = ly;
-            *ny = -lx;
-            code = ORC_RIGHT;
-        }
-        /* u = (closest point of the leg line to V) - V */
-        double s = Vx * lx + Vy * ly;
-        *ux = s * lx - Vx;
-        *uy = s * ly - Vy;
-        return code;
-    }
-    /* already in contact: cut-off disc D(P/dt, R/dt) */
-    double wx = Vx - Px / dt, wy = Vy - Py / dt;
-    double wl = sqrt(wx * wx + wy * wy);
-    if (wl > 0.0) {
-        *nx = wx / wl;
-        *ny = wy / wl;
-    } else if (dist2 > 0.0) {
-        double pl = sqrt(dist2);
-        *nx = -Px / pl;
-        *ny = -Py / pl;
-    } else {
-        *nx = i_before_j ? 1.0 : -1.0;
-        *ny = 0.0;
-    }
-    *ux = (R / dt - wl) * *nx;
-    *uy = (R / dt - wl) * *ny;
-    return ORC_OVERLAP;
+    return obstacle(Px, Py, Vx, Vy, R, tau, dt, i_before_j, ux, uy, nx, ny);
 }
 
-/* ------------------------------------------------------------------ */
-/* 2D LP by enumeration                                                */
-/* ------------------------------------------------------------------ */
-
-/* Feasible for every half-plane n.(v - q) >= -shift and inside the disc. */
-static int feasible(int m, const halfplane *h, double shift, double vmax, double vx, double vy)
-{
-    if (vx * vx + vy * vy > vmax * vmax * (1.0 + 1e-12) + 1e-12) return 0;
-    for (int k = 0; k < m; ++k) {
-        double s = h[k].nx * (vx - h[k].qx) + h[k].ny * (vy - h[k].qy);
-        if (s < -shift - ORC_TOL) return 0;
-    }
-    return 1;
-}
-
-typedef struct {
-    int found;
-    double bx, by, bd;
-} best_t;
-
-static void consider(best_t *b, int m, const halfplane *h, double shift, double vmax, double px,
-                     double py, double vhx, double vhy)
-{
-    if (!isfinite(px) || !isfinite(py)) return;
-    if (!feasible(m, h, shift, vmax, px, py)) return;
-    double d = (px - vhx) * (px - vhx) + (py - vhy) * (py - vhy);
-    if (!b->found || d < b->bd) { b->found = 1; b->bx = px; b->by = py; b->bd = d; }
-}
-
-/*
- * argmin |v - vhat| over the disc |v| <= vmax and the half-planes
- * n_k.(v - q_k) >= -shift.  The minimiser of a strictly convex function over
- * this set is vhat itself, the radial clip of vhat, the projection of vhat
- * onto one boundary line, a line-circle crossing, or a line-line crossing;
- * all of them are tried.  Returns 1 and writes the minimiser if the set is
- * non-empty, else 0.
- */
+/* The 2D program by enumeration; see project(). */
 int oracle_project(int m, const halfplane *h, double shift, double vmax, double vhx, double vhy,
                    double *ox, double *oy)
 {
-    best_t b = {0, 0.0, 0.0, 0.0};
-    consider(&b, m, h, shift, vmax, vhx, vhy, vhx, vhy);
-    double vl = sqrt(vhx * vhx + vhy * vhy);
-    if (vl > 0.0) consider(&b, m, h, shift, vmax, vmax * vhx / vl, vmax * vhy / vl, vhx, vhy);
-    for (int k = 0; k < m; ++k) {
-        /* boundary line: n_k.v = c_k */
-        double c = h[k].nx * h[k].qx + h[k].ny * h[k].qy - shift;
-        double t = c - (h[k].nx * vhx + h[k].ny * vhy);
-        consider(&b, m, h, shift, vmax, vhx + t * h[k].nx, vhy + t * h[k].ny, vhx, vhy);
-        double hh = vmax * vmax - c * c;
-        if (hh >= 0.0) {
-            double r = sqrt(hh);
-            double dx = -h[k].ny, dy = h[k].nx;
-            consider(&b, m, h, shift, vmax, c * h[k].nx + r * dx, c * h[k].ny + r * dy, vhx, vhy);
-            consider(&b, m, h, shift, vmax, c * h[k].nx - r * dx, c * h[k].ny - r * dy, vhx, vhy);
-        }
-    }
-    for (int k = 0; k < m; ++k) {
-        double ck = h[k].nx * h[k].qx + h[k].ny * h[k].qy - shift;
-        for (int l = k + 1; l < m; ++l) {
-            double cl = h[l].nx * h[l].qx + h[l].ny * h[l].qy - shift;
-            double det = h[k].nx * h[l].ny - h[k].ny * h[l].nx;
-            if (det == 0.0) continue;
-            double px = (ck * h[l].ny - cl * h[k].ny) / det;
-            double py = (h[k].nx * cl - h[l].nx * ck) / det;
-            consider(&b, m, h, shift, vmax, px, py, vhx, vhy);
-        }
-    }
-    if (!b.found) return 0;
-    *ox = b.bx;
-    *oy = b.by;
-    return 1;
+    return project(m, h, shift, vmax, vhx, vhy, ox, oy);
 }
 
-/* largest violation max_k n_k.(q_k - v) */
-static double max_violation(int m, const halfplane *h, double vx, double vy)
-{
-    double f = -INFINITY;
-    for (int k = 0; k < m; ++k) {
-        double s = h[k].nx * (h[k].qx - vx) + h[k].ny * (h[k].qy - vy);
-        if (s > f) f = s;
-    }
-    return f;
-}
-
-static void consider_mm(int m, const halfplane *h, double vmax, double vx, double vy, int *found,
-                        double *bf, double *bx, double *by)
-{
-    if (!isfinite(vx) || !isfinite(vy)) return;
-    if (vx * vx + vy * vy > vmax * vmax * (1.0 + 1e-12) + 1e-12) return;
-    double f = max_violation(m, h, vx, vy);
-    if (!*found || f < *bf) { *found = 1; *bf = f; *bx = vx; *by = vy; }
-}
-
-/*
- * d* = min over |v| <= vmax of max_k n_k.(q_k - v).  The minimum of this
- * convex piecewise-linear function over the disc sits where three pieces are
- * equal, where two pieces are equal on the circle, or on the circle at the
- * point that maximises a single n_k.v (v = vmax n_k); all are tried.
- */
+/* The least penetration by enumeration; see min_max(). */
 double oracle_min_max(int m, const halfplane *h, double vmax, double *ox, double *oy)
 {
-    int found = 0;
-    double bf = 0.0, bx = 0.0, by = 0.0;
-    for (int k = 0; k < m; ++k)
-        consider_mm(m, h, vmax, vmax * h[k].nx, vmax * h[k].ny, &found, &bf, &bx, &by);
-    for (int k = 0; k < m; ++k) {
-        double ck = h[k].nx * h[k].qx + h[k].ny * h[k].qy;
-        for (int l = k + 1; l < m; ++l) {
-            double cl = h[l].nx * h[l].qx + h[l].ny * h[l].qy;
-            /* equal violation: (n_k - n_l).v = c_k - c_l */
-            double ax = h[k].nx - h[l].nx, ay = h[k].ny - h[l].ny, c = ck - cl;
-            double a2 = ax * ax + ay * ay;
-            if (a2 == 0.0) continue;
-            double px = c * ax / a2, py = c * ay / a2;
-            double hh = vmax * vmax - (px * px + py * py);
-            if (hh < 0.0) continue;
-            double r = sqrt(hh / a2);
-            consider_mm(m, h, vmax, px - r * ay, py + r * ax, &found, &bf, &bx, &by);
-            consider_mm(m, h, vmax, px + r * ay, py - r * ax, &found, &bf, &bx, &by);
-            for (int p = l + 1; p < m; ++p) {
-                double cp = h[p].nx * h[p].qx + h[p].ny * h[p].qy;
-                /* n.v + t = c for the three pieces (Cramer's rule) */
-                double a11 = h[k].nx, a12 = h[k].ny;
-                double a21 = h[l].nx, a22 = h[l].ny;
-                double a31 = h[p].nx, a32 = h[p].ny;
-                double det = a11 * (a22 - a32) - a12 * (a21 - a31) + (a21 * a32 - a22 * a31);
-                if (det == 0.0) continue;
-                double dxn = ck * (a22 - a32) - a12 * (cl - cp) + (cl * a32 - a22 * cp);
-                double dyn = a11 * (cl - cp) - ck * (a21 - a31) + (a21 * cp - cl * a31);
-                consider_mm(m, h, vmax, dxn / det, dyn / det, &found, &bf, &bx, &by);
-            }
-        }
-    }
-    *ox = bx;
-    *oy = by;
-    return found ? bf : -INFINITY;
+    return min_max(m, h, vmax, ox, oy);
 }
 
 /* ------------------------------------------------------------------ */
@@ -469,35 +298,22 @@ int oracle_agent_velocity(int64_t n_total, const float *pos, const float *vel, c
     const float *x = pos, *y = pos + n_total;
     const float *vx = vel, *vy = vel + n_total;
     halfplane hbuf[64];
-    halfplane *h = hp_out ? hp_out : hbuf;
-    double vmax = p->max_speed;
+    double Px[64], Py[64], Vx[64], Vy[64], Rs[64];
+    int first[64];
     for (int32_t t = 0; t < m; ++t) {
         int64_t j = nbr[t];
-        double Px = (double)x[j] - (double)x[i], Py = (double)y[j] - (double)y[i];
-        double Vx = (double)vx[i] - (double)vx[j], Vy = (double)vy[i] - (double)vy[j];
+        Px[t] = (double)x[j] - (double)x[i];
+        Py[t] = (double)y[j] - (double)y[i];
+        Vx[t] = (double)vx[i] - (double)vx[j];
+        Vy[t] = (double)vy[i] - (double)vy[j];
         double ri = rad ? (double)rad[i] : (double)p->radius;
         double rj = rad ? (double)rad[j] : (double)p->radius;
-        double ux, uy, nx, ny;
-        int code = oracle_halfplane(Px, Py, Vx, Vy, ri + rj, p->time_horizon, p->dt, i < j,
-                                    &ux, &uy, &nx, &ny);
-        if (branch_out) branch_out[t] = code;
-        h[t].qx = (double)vx[i] + 0.5 * ux;
-        h[t].qy = (double)vy[i] + 0.5 * uy;
-        h[t].nx = nx;
-        h[t].ny = ny;
+        Rs[t] = ri + rj;
+        first[t] = i < j;
     }
-    if (oracle_project(m, h, 0.0, vmax, vhx, vhy, ox, oy)) {
-        if (dstar) *dstar = NAN;
-        return 0;
-    }
-    double mx, my;
-    double d = oracle_min_max(m, h, vmax, &mx, &my);
-    if (dstar) *dstar = d;
-    if (!oracle_project(m, h, d + ORC_DELTA, vmax, vhx, vhy, ox, oy)) {
-        *ox = mx;
-        *oy = my;
-    }
-    return 1;
+    return choose(m, Px, Py, Vx, Vy, Rs, first, (double)vx[i], (double)vy[i], p->time_horizon,
+                  p->dt, p->max_speed, vhx, vhy, ox, oy, dstar, hp_out ? hp_out : hbuf,
+                  branch_out);
 }
 
 static int scene_of(int32_t n_scenes, const int64_t *off, int64_t i)

@@ -25,7 +25,7 @@ struct orca_ctx {
     int32_t max_scenes = 0, k_max = 0, tape_steps = 0;
     hipStream_t stream = nullptr;
     uint32_t max_cells = 0;
-    int32_t n_tiles = 0, fb_blocks = 0;
+    int32_t n_tiles = 0, cus = 0;
 
     // device scratch
     int32_t *off = nullptr;
@@ -42,6 +42,8 @@ struct orca_ctx {
     int32_t *sid = nullptr, *skey = nullptr, *inv = nullptr;
     int32_t *nbr = nullptr, *ncount = nullptr;
     orca::FallbackItem *fb_list = nullptr;
+    double2 *stash_n = nullptr;
+    double *stash_b = nullptr;
     std::vector<void *> allocs;
 
     // scene set currently on the device
@@ -64,6 +66,17 @@ struct orca_ctx {
     hipEvent_t ev[ORCA_PROF_STAGES + 1] = {};
     double stage_ms[ORCA_PROF_STAGES] = {0};
     int64_t prof_steps = 0, prof_fallback = 0;
+
+    // launch shapes (orca_autotune picks them)
+    int32_t knn_block = 256, fb_waves_per_cu = 16;
+
+    // step graph: one captured step replayed by orca_step_graph
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    const void *graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t graph_scene_version = 0, scene_version = 0;
+    int32_t graph_knn_block = 0, graph_fb = 0;
 
     char err[512] = {0};
 };
@@ -180,6 +193,7 @@ int use_scenes(orca_ctx *ctx, int32_t n_scenes, const int64_t *off, const orca_p
                                   ctx->stream));
     ctx->uploaded = true;
     ctx->grid_valid = false;
+    ++ctx->scene_version;
     return ORCA_OK;
 }
 
@@ -189,7 +203,9 @@ orca::Plan make_plan(const orca_ctx *ctx)
     p.n = (int32_t)ctx->n;
     p.n_scenes = ctx->n_scenes;
     p.ld = (int32_t)ctx->max_agents;
-    p.fb_blocks = ctx->fb_blocks;
+    p.cus = ctx->cus;
+    p.knn_block = ctx->knn_block;
+    p.fb_waves_per_cu = ctx->fb_waves_per_cu;
     p.max_cells = ctx->max_cells;
     p.off = ctx->off;
     p.sp = ctx->sp;
@@ -211,6 +227,8 @@ orca::Plan make_plan(const orca_ctx *ctx)
     p.nbr = ctx->nbr;
     p.ncount = ctx->ncount;
     p.fb_list = ctx->fb_list;
+    p.stash_n = ctx->stash_n;
+    p.stash_b = ctx->stash_b;
     return p;
 }
 
@@ -248,8 +266,21 @@ int run_pass(orca_ctx *ctx, const orca::Plan &pl, const float *grid_pos, const f
     return ORCA_OK;
 }
 
+void drop_graph(orca_ctx *c)
+{
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
 void free_all(orca_ctx *c)
 {
+    drop_graph(c);
+    if (c->cap_stream) {
+        (void)hipStreamDestroy(c->cap_stream);
+        c->cap_stream = nullptr;
+    }
     for (int i = 0; i <= ORCA_PROF_STAGES; ++i)
         if (c->ev[i]) {
             (void)hipEventDestroy(c->ev[i]);
@@ -294,7 +325,7 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
             cus = prop.multiProcessorCount;
     }
-    ctx->fb_blocks = cus * 16;
+    ctx->cus = cus;
     // each scene's agents split into chunks of kBboxChunk: at most A / chunk + S chunks
     ctx->max_chunks = max_agents / orca::kBboxChunk + max_scenes + 1;
 
@@ -325,7 +356,9 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->inv, sizeof(int32_t) * A) &&
               alloc((void **)&ctx->nbr, sizeof(int32_t) * A * (size_t)k_max) &&
               alloc((void **)&ctx->ncount, sizeof(int32_t) * A) &&
-              alloc((void **)&ctx->fb_list, sizeof(orca::FallbackItem) * A);
+              alloc((void **)&ctx->fb_list, sizeof(orca::FallbackItem) * A) &&
+              alloc((void **)&ctx->stash_n, sizeof(double2) * A * (size_t)k_max) &&
+              alloc((void **)&ctx->stash_b, sizeof(double) * A * (size_t)k_max);
     if (!ok) {
         free_all(ctx);
         delete ctx;
@@ -422,6 +455,103 @@ int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
     for (int32_t t = 0; t < n_steps; ++t) {
         rc = run_pass(ctx, pl, pos, vel);
         if (rc != ORCA_OK) return rc;
+    }
+    return ORCA_OK;
+}
+
+int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
+                    const orca_params *params, float *pos, float *vel, float *pref_vel,
+                    const float *goals, int32_t n_steps)
+{
+    if (!ctx) return ORCA_EINVAL;
+    if (n_steps < 1) return fail(ctx, ORCA_EINVAL, "n_steps must be >= 1");
+    if (ctx->profiling) return fail(ctx, ORCA_ESTATE, "stop profiling before replaying a graph");
+    int rc = use_scenes(ctx, n_scenes, scene_offsets, params);
+    if (rc != ORCA_OK) return rc;
+    if (ctx->n > 0 && (!pos || !vel || !pref_vel))
+        return fail(ctx, ORCA_EINVAL, "pos, vel and pref_vel must be non-NULL");
+    ctx->grid_valid = false;
+    const void *key[4] = {pos, vel, pref_vel, goals};
+    const bool fresh = ctx->graph_exec && memcmp(key, ctx->graph_key, sizeof(key)) == 0 &&
+                       ctx->graph_scene_version == ctx->scene_version &&
+                       ctx->graph_knn_block == ctx->knn_block &&
+                       ctx->graph_fb == ctx->fb_waves_per_cu;
+    if (!fresh) {
+        drop_graph(ctx);
+        if (!ctx->cap_stream) HIP_OK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        // the uploads of use_scenes must be done before the captured kernels replay
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        orca::Plan pl = make_plan(ctx);
+        pl.out.pos = pos;
+        pl.out.vel = vel;
+        pl.out.pref = pref_vel;
+        pl.out.goals = goals;
+        hipStream_t user = ctx->stream;
+        ctx->stream = ctx->cap_stream;
+        hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            rc = run_pass(ctx, pl, pos, vel);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
+            ctx->graph = g;
+            if (rc == ORCA_OK && e2 != hipSuccess) rc = hip_fail(ctx, e2, "hipStreamEndCapture");
+        } else {
+            rc = hip_fail(ctx, e, "hipStreamBeginCapture");
+        }
+        ctx->stream = user;
+        if (rc != ORCA_OK) {
+            drop_graph(ctx);
+            return rc;
+        }
+        HIP_OK(hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0));
+        memcpy(ctx->graph_key, key, sizeof(key));
+        ctx->graph_scene_version = ctx->scene_version;
+        ctx->graph_knn_block = ctx->knn_block;
+        ctx->graph_fb = ctx->fb_waves_per_cu;
+    }
+    for (int32_t t = 0; t < n_steps; ++t) HIP_OK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    return ORCA_OK;
+}
+
+int orca_autotune(orca_ctx *ctx, const float *pos, const float *vel, const float *pref_vel,
+                  const float *goals, float *new_vel, int32_t reps, int32_t *choice)
+{
+    if (!ctx) return ORCA_EINVAL;
+    if (reps < 1) return fail(ctx, ORCA_EINVAL, "reps must be >= 1");
+    if (!ctx->grid_valid || pos != ctx->grid_pos)
+        return fail(ctx, ORCA_ESTATE, "orca_build_grid must be called first on the same pos");
+    static const int32_t blocks[] = {64, 128, 256, 512};
+    static const int32_t waves[] = {4, 8, 16, 32};
+    const bool was = ctx->profiling;
+    int rc = orca_profile(ctx, 1);
+    if (rc != ORCA_OK) return rc;
+    double best_knn = 1e300, best_fb = 1e300;
+    int32_t knn_block = ctx->knn_block, fb = ctx->fb_waves_per_cu;
+    for (int t = 0; t < 4; ++t) {
+        ctx->knn_block = blocks[t];
+        ctx->fb_waves_per_cu = waves[t];
+        orca_profile(ctx, 1);
+        for (int32_t r = 0; r < reps; ++r) {
+            rc = orca_compute_velocities(ctx, pos, vel, pref_vel, goals, new_vel, nullptr, nullptr);
+            if (rc != ORCA_OK) break;
+        }
+        if (rc != ORCA_OK) break;
+        if (ctx->stage_ms[1] < best_knn) {
+            best_knn = ctx->stage_ms[1];
+            knn_block = blocks[t];
+        }
+        if (ctx->stage_ms[3] < best_fb) {
+            best_fb = ctx->stage_ms[3];
+            fb = waves[t];
+        }
+    }
+    ctx->knn_block = knn_block;
+    ctx->fb_waves_per_cu = fb;
+    orca_profile(ctx, was ? 1 : 0);
+    if (rc != ORCA_OK) return rc;
+    if (choice) {
+        choice[0] = knn_block;
+        choice[1] = fb;
     }
     return ORCA_OK;
 }

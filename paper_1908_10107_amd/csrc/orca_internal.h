@@ -11,8 +11,8 @@ constexpr int kScanBlock = 256;
 constexpr int kScanTile = kScanItems * kScanBlock;  // cells per scan tile
 constexpr int kLpBlock = 64;                        // one wave per LP block
 constexpr int kBboxChunk = 8192;                    // agents per bounding-box block
-constexpr double kCellMargin = 1.0 + 1.0 / 1024.0;  // cell side / neighbor_dist
 constexpr double kDelta = 1e-5;  // relaxation of the least-penetration second stage (m/s)
+constexpr double kCellMargin = 1.0 + 1.0 / 1024.0;  // cell side / neighbor_dist
 
 // Per-scene parameters as the kernels read them.
 struct SceneDev {
@@ -33,11 +33,14 @@ struct Counters {
     uint32_t pad[2];
 };
 
-// An agent whose 2D program was empty: its sorted index, the constraint at
-// which the program failed, and the optimum of the constraints before it.
+// An agent whose projection was empty, with what the fallback needs to
+// finish it without touching the agent arrays again: sorted index, id, number
+// of half-planes, the row at which the projection failed, the optimum of the
+// rows before it, the preferred velocity, max speed, dt and position.
 struct FallbackItem {
-    int32_t s, fail;
-    double vx, vy;
+    int32_t s, id, m, fail;
+    double vx, vy, vhx, vhy;
+    float vmax, dt, mex, mey;
 };
 
 // Where the velocity kernels put their results.  Step mode has pos != nullptr.
@@ -54,7 +57,9 @@ struct OutArgs {
 
 // Device buffers and sizes of one launch sequence.
 struct Plan {
-    int32_t n, n_scenes, ld, fb_blocks, n_chunks;
+    int32_t n, n_scenes, ld, cus, n_chunks;
+    int32_t knn_block;        // threads per k_knn block (64..512)
+    int32_t fb_waves_per_cu;  // persistent k_fallback waves per CU
     uint32_t max_cells;
     const int32_t *off;
     const SceneDev *sp;
@@ -69,6 +74,8 @@ struct Plan {
     int32_t *sid, *skey, *inv;
     int32_t *nbr, *ncount;
     FallbackItem *fb_list;
+    double2 *stash_n;  // [k_max, ld] half-plane normals of fallback slots
+    double *stash_b;   // [k_max, ld] half-plane offsets
     OutArgs out;
 };
 

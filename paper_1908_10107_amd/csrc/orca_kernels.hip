@@ -367,11 +367,12 @@ __global__ __launch_bounds__(256) void k_fill_vel(const float *__restrict__ vel,
 // K nearest of each agent (sorted order s) among the agents of its 3x3 cells,
 // strictly inside neighbor_dist, nearest first, ties by agent id.  The running
 // list holds (float32 bits of d2) << 32 | id, so one 64-bit compare orders by
-// (d2, id).  Writes nbr[k * ld + s] = neighbour id and ncount[s].
+// (d2, id).  Writes nbr[k * ld + s] = the neighbour's sorted index and ncount[s].
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_knn(const float4 *__restrict__ sorted,
+__global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
                                              const int32_t *__restrict__ sid,
                                              const int32_t *__restrict__ skey,
+                                             const int32_t *__restrict__ inv,
                                              const int32_t *__restrict__ cell_start,
                                              const GridDev *__restrict__ grid,
                                              const int32_t *__restrict__ agent_scene,
@@ -400,8 +401,9 @@ __global__ __launch_bounds__(256) void k_knn(const float4 *__restrict__ sorted,
     for (int k = 0; k < KMAX; ++k) best[k] = ~0ull;
     uint64_t worst = ~0ull;  // current K-th entry
     const int32_t c0 = max(cx - 1, 0), c1 = min(cx + 1, g.nx - 1);
-    for (int32_t dy = -1; dy <= 1; ++dy) {
-        const int32_t row = cy + dy;
+    // own row first: the list fills with near candidates and prunes the rest
+    for (int32_t r = 0; r < 3; ++r) {
+        const int32_t row = cy + (r == 0 ? 0 : (r == 1 ? -1 : 1));
         if (row < 0 || row >= g.ny) continue;
         const int32_t rb = g.base + row * g.nx;
         const int32_t beg = cell_start[rb + c0], end = cell_start[rb + c1 + 1];
@@ -433,7 +435,7 @@ __global__ __launch_bounds__(256) void k_knn(const float4 *__restrict__ sorted,
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         if (k < K && best[k] != ~0ull) {
-            nbr[(int64_t)k * ld + s] = (int32_t)(uint32_t)(best[k] & 0xffffffffu);
+            nbr[(int64_t)k * ld + s] = inv[(uint32_t)(best[k] & 0xffffffffu)];
             cnt = k + 1;
         }
     }
@@ -451,7 +453,7 @@ static_assert(kLpStride == kLpBlock, "LP constraint stride must equal the LP blo
 // Load agent s's neighbours, build the half-planes into the lane's LDS column.
 __device__ __forceinline__ int build_constraints(const Lane &L, int32_t s, int32_t id, float4 me,
                                                  const SceneDev &p, const float4 *__restrict__ sorted,
-                                                 const int32_t *__restrict__ inv,
+                                                 const int32_t *__restrict__ sid,
                                                  const int32_t *__restrict__ nbr, int32_t ld,
                                                  const int32_t *__restrict__ ncount,
                                                  int32_t *__restrict__ nbr_out, int32_t krow)
@@ -461,8 +463,9 @@ __device__ __forceinline__ int build_constraints(const Lane &L, int32_t s, int32
     const double tau = (double)p.tau, dt = (double)p.dt;
     const double vix = (double)me.z, viy = (double)me.w;
     for (int k = 0; k < m; ++k) {
-        const int32_t jid = nbr[(int64_t)k * ld + s];
-        const float4 o = sorted[inv[jid]];
+        const int32_t j = nbr[(int64_t)k * ld + s];
+        const float4 o = sorted[j];
+        const int32_t jid = sid[j];
         const double Px = (double)o.x - (double)me.x, Py = (double)o.y - (double)me.y;
         const double Vx = vix - (double)o.z, Vy = viy - (double)o.w;
         double ux, uy, nx, ny;
@@ -502,7 +505,7 @@ __device__ __forceinline__ void preferred_velocity(const SceneDev &p, float4 me,
     }
 }
 
-__device__ __forceinline__ void write_result(const OutArgs &o, const SceneDev &p, float4 me,
+__device__ __forceinline__ void write_result(const OutArgs &o, float mex, float mey, float dtf,
                                              int32_t id, int32_t n, double vx, double vy,
                                              double vhx, double vhy, uint8_t status)
 {
@@ -512,9 +515,9 @@ __device__ __forceinline__ void write_result(const OutArgs &o, const SceneDev &p
         o.new_vel[n + id] = (float)vy;
     }
     if (o.pos) {
-        const double dt = (double)p.dt;
-        o.pos[id] = (float)((double)me.x + dt * vx);
-        o.pos[n + id] = (float)((double)me.y + dt * vy);
+        const double dt = (double)dtf;
+        o.pos[id] = (float)((double)mex + dt * vx);
+        o.pos[n + id] = (float)((double)mey + dt * vy);
         o.vel[id] = (float)vx;
         o.vel[n + id] = (float)vy;
         if (o.goals) {
@@ -526,45 +529,55 @@ __device__ __forceinline__ void write_result(const OutArgs &o, const SceneDev &p
 }
 
 // One lane per agent in cell order.  Feasible agents finish here; an agent
-// whose 2D program is empty is appended to the fallback list with the index
-// where it failed and the optimum of the constraints before it (one atomic
-// per wave).
+// whose projection is empty is handed to the fallback list with everything
+// k_fallback needs (one atomic per wave), and its half-planes go to column
+// `slot` of the stash.
 template <int KMAX>
 __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sorted,
                                                  const int32_t *__restrict__ sid,
-                                                 const int32_t *__restrict__ inv,
                                                  const int32_t *__restrict__ agent_scene,
                                                  const SceneDev *__restrict__ sp, int32_t n,
                                                  const int32_t *__restrict__ nbr, int32_t ld,
                                                  const int32_t *__restrict__ ncount,
                                                  OutArgs out, FallbackItem *__restrict__ fb_list,
+                                                 double2 *__restrict__ stash_n,
+                                                 double *__restrict__ stash_b,
                                                  Counters *__restrict__ counters)
 {
     __shared__ double2 s_n[KMAX * kLpBlock];
     __shared__ double s_b[KMAX * kLpBlock];
     const int32_t s = blockIdx.x * kLpBlock + threadIdx.x;
+    const Lane L{s_n + threadIdx.x, s_b + threadIdx.x};
     bool need_fb = false;
-    FallbackItem item;
+    FallbackItem it{};
     if (s < n) {
-        const Lane L{s_n + threadIdx.x, s_b + threadIdx.x};
         const float4 me = sorted[s];
         const int32_t id = sid[s];
         const SceneDev p = sp[agent_scene[id]];
         double vhx, vhy;
         preferred_velocity(p, me, id, n, out.pref, out.goals, vhx, vhy);
-        const int m = build_constraints(L, s, id, me, p, sorted, inv, nbr, ld, ncount,
-                                        out.nbr_out, out.krow);
+        const double vmax = (double)p.vmax;
         double vx, vy;
-        disc_clip((double)p.vmax, vhx, vhy, vx, vy);
-        const int fail = lp2_project(L, m, 0, 0.0, (double)p.vmax, vhx, vhy, vx, vy);
+        disc_clip(vmax, vhx, vhy, vx, vy);
+        const int m = build_constraints(L, s, id, me, p, sorted, sid, nbr, ld, ncount,
+                                        out.nbr_out, out.krow);
+        const int fail = lp2_project(L, m, 0, 0.0, vmax, vhx, vhy, vx, vy);
         if (fail < 0) {
-            write_result(out, p, me, id, n, vx, vy, vhx, vhy, 0);
+            write_result(out, me.x, me.y, p.dt, id, n, vx, vy, vhx, vhy, 0);
         } else {
             need_fb = true;
-            item.s = s;
-            item.fail = fail;
-            item.vx = vx;
-            item.vy = vy;
+            it.s = s;
+            it.id = id;
+            it.m = m;
+            it.fail = fail;
+            it.vx = vx;
+            it.vy = vy;
+            it.vhx = vhx;
+            it.vhy = vhy;
+            it.vmax = p.vmax;
+            it.dt = p.dt;
+            it.mex = me.x;
+            it.mey = me.y;
         }
     }
     const uint64_t mask = __ballot(need_fb);
@@ -576,24 +589,26 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
         const int leader = __ffsll((unsigned long long)mask) - 1;
         if ((int)lane == leader) slot0 = atomicAdd(&counters->n_fallback, (uint32_t)__popcll(mask));
         slot0 = __shfl(slot0, leader, 64);
-        if (need_fb) fb_list[slot0 + before] = item;
+        if (need_fb) {
+            const uint32_t slot = slot0 + before;
+            fb_list[slot] = it;
+            for (int k = 0; k < it.m; ++k) {
+                stash_n[(int64_t)k * ld + slot] = L.N(k);
+                stash_b[(int64_t)k * ld + slot] = L.B(k);
+            }
+        }
     }
 }
 
-// Persistent over the fallback list: rebuild the half-planes, find the least
-// penetration d* from the 2D program's last optimum, then take the point
+// Persistent over the fallback list: load the half-planes k_lp stashed, find
+// the least penetration d* from the projection's last optimum (the rows
+// before the failed one are satisfied there with t = 0), then take the point
 // closest to vhat among those within d* + delta of every half-plane.
 template <int KMAX>
-__global__ __launch_bounds__(kLpBlock) void k_fallback(const float4 *__restrict__ sorted,
-                                                       const int32_t *__restrict__ sid,
-                                                       const int32_t *__restrict__ inv,
-                                                       const int32_t *__restrict__ agent_scene,
-                                                       const SceneDev *__restrict__ sp,
-                                                       int32_t n, const int32_t *__restrict__ nbr,
-                                                       int32_t ld,
-                                                       const int32_t *__restrict__ ncount,
-                                                       OutArgs out,
+__global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, int32_t ld,
                                                        const FallbackItem *__restrict__ fb_list,
+                                                       const double2 *__restrict__ stash_n,
+                                                       const double *__restrict__ stash_b,
                                                        const Counters *__restrict__ counters)
 {
     __shared__ double2 s_n[KMAX * kLpBlock];
@@ -602,24 +617,22 @@ __global__ __launch_bounds__(kLpBlock) void k_fallback(const float4 *__restrict_
     const Lane L{s_n + threadIdx.x, s_b + threadIdx.x};
     for (uint32_t idx = blockIdx.x * kLpBlock + threadIdx.x; idx < count;
          idx += gridDim.x * kLpBlock) {
-        const FallbackItem item = fb_list[idx];
-        const int32_t s = item.s;
-        const float4 me = sorted[s];
-        const int32_t id = sid[s];
-        const SceneDev p = sp[agent_scene[id]];
-        double vhx, vhy;
-        preferred_velocity(p, me, id, n, out.pref, out.goals, vhx, vhy);
-        const int m = build_constraints(L, s, id, me, p, sorted, inv, nbr, ld, ncount, nullptr, 0);
-        const double vmax = (double)p.vmax;
-        double vx = item.vx, vy = item.vy;
-        const double d = lp3_least_penetration(L, m, item.fail, vmax, vx, vy);
+        const FallbackItem it = fb_list[idx];
+        const int m = it.m;
+        for (int k = 0; k < m; ++k) {
+            L.n[k * kLpBlock] = stash_n[(int64_t)k * ld + idx];
+            L.b[k * kLpBlock] = stash_b[(int64_t)k * ld + idx];
+        }
+        const double vmax = (double)it.vmax;
+        double vx = it.vx, vy = it.vy;
+        const double d = lp3_least_penetration(L, m, it.fail, vmax, vx, vy);
         double wx, wy;
-        disc_clip(vmax, vhx, vhy, wx, wy);
-        if (lp2_project(L, m, 0, d + kDelta, vmax, vhx, vhy, wx, wy) < 0) {
+        disc_clip(vmax, it.vhx, it.vhy, wx, wy);
+        if (lp2_project(L, m, 0, d + kDelta, vmax, it.vhx, it.vhy, wx, wy) < 0) {
             vx = wx;
             vy = wy;
         }
-        write_result(out, p, me, id, n, vx, vy, vhx, vhy, 1);
+        write_result(out, it.mex, it.mey, it.dt, it.id, n, vx, vy, it.vhx, it.vhy, 1);
     }
 }
 
@@ -629,8 +642,9 @@ template <int KMAX>
 hipError_t launch_knn_k(const Plan &pl, hipStream_t st)
 {
     const int32_t n = pl.n;
-    hipLaunchKernelGGL(k_knn<KMAX>, dim3((n + 255) / 256), dim3(256), 0, st, pl.sorted, pl.sid,
-                       pl.skey, pl.cell_start, pl.grid, pl.agent_scene, pl.sp, n, pl.nbr, pl.ld,
+    const int32_t bs = pl.knn_block;
+    hipLaunchKernelGGL(k_knn<KMAX>, dim3((n + bs - 1) / bs), dim3(bs), 0, st, pl.sorted, pl.sid,
+                       pl.skey, pl.inv, pl.cell_start, pl.grid, pl.agent_scene, pl.sp, n, pl.nbr, pl.ld,
                        pl.ncount, pl.counters);
     return hipGetLastError();
 }
@@ -640,21 +654,19 @@ hipError_t launch_lp_k(const Plan &pl, hipStream_t st)
 {
     const int32_t n = pl.n;
     const int32_t gl = (n + kLpBlock - 1) / kLpBlock;
-    hipLaunchKernelGGL(k_lp<KMAX>, dim3(gl), dim3(kLpBlock), 0, st, pl.sorted, pl.sid, pl.inv,
+    hipLaunchKernelGGL(k_lp<KMAX>, dim3(gl), dim3(kLpBlock), 0, st, pl.sorted, pl.sid,
                        pl.agent_scene, pl.sp, n, pl.nbr, pl.ld, pl.ncount, pl.out, pl.fb_list,
-                       pl.counters);
+                       pl.stash_n, pl.stash_b, pl.counters);
     return hipGetLastError();
 }
 
 template <int KMAX>
 hipError_t launch_fallback_k(const Plan &pl, hipStream_t st)
 {
-    const int32_t n = pl.n;
-    const int32_t gl = (n + kLpBlock - 1) / kLpBlock;
-    const int32_t gf = min(gl, pl.fb_blocks);
-    hipLaunchKernelGGL(k_fallback<KMAX>, dim3(gf), dim3(kLpBlock), 0, st, pl.sorted, pl.sid,
-                       pl.inv, pl.agent_scene, pl.sp, n, pl.nbr, pl.ld, pl.ncount, pl.out,
-                       pl.fb_list, pl.counters);
+    // persistent: fb_waves_per_cu one-wave blocks per CU loop over the device-side list
+    const int32_t gf = max(1, min((pl.n + kLpBlock - 1) / kLpBlock, pl.fb_waves_per_cu * pl.cus));
+    hipLaunchKernelGGL(k_fallback<KMAX>, dim3(gf), dim3(kLpBlock), 0, st, pl.out, pl.n, pl.ld,
+                       pl.fb_list, pl.stash_n, pl.stash_b, pl.counters);
     return hipGetLastError();
 }
 

@@ -24,6 +24,11 @@ struct double2 {
 inline double2 make_double2(double x, double y) { return double2{x, y}; }
 #endif
 
+// Work-counting hook for offline analysis builds; compiles to nothing here.
+#ifndef ORCA_COUNT
+#define ORCA_COUNT(what)
+#endif
+
 namespace orca {
 
 #ifndef ORCA_LP_STRIDE
@@ -129,7 +134,7 @@ struct Interval {
         lo_d = raise ? den : lo_d;
         hi_n = lower ? -num : hi_n;
         hi_d = lower ? -den : hi_d;
-        bad = bad || (!up && !down && num > 0.0);
+        bad = bad | (!up & !down & (num > 0.0));
     }
     ORCA_HD inline bool empty() const { return bad || lo_n * hi_d > hi_n * lo_d; }
     // t clamped into the interval, as a fraction (t_n / t_d)
@@ -162,7 +167,9 @@ ORCA_HD inline int lp2_project(const Lane &L, int m, int from, double relax, dou
     for (int k = from; k < m; ++k) {
         const double2 nk = L.N(k);
         const double bk = L.B(k) - relax;
+        ORCA_COUNT(lp2_check);
         if (nk.x * vx + nk.y * vy >= bk) continue;
+        ORCA_COUNT(lp2_line);
         double h2 = vm2 - bk * bk;
         if (h2 < 0.0) {
             if (bk > 0.0) return k;  // the line misses the disc on the far side
@@ -174,6 +181,7 @@ ORCA_HD inline int lp2_project(const Lane &L, int m, int from, double relax, dou
         for (int j = 0; j < k; ++j) {
             const double2 nj = L.N(j);
             const double bj = L.B(j) - relax;
+            ORCA_COUNT(lp2_inner);
             iv.add(nj.y * nk.x - nj.x * nk.y, bj - bk * (nj.x * nk.x + nj.y * nk.y));
         }
         if (iv.empty()) return k;
@@ -233,7 +241,9 @@ ORCA_HD inline bool lp2_plane(const Lane &L, int k, double2 nk, double bk, doubl
     for (int i = -1; i < k; ++i) {
         double mx, my, ci;
         plane_row(L, i, nk, bk, mx, my, ci);
+        ORCA_COUNT(plane_check);
         if (mx * vx + my * vy >= ci) continue;
+        ORCA_COUNT(plane_line);
         const double mm = mx * mx + my * my;
         if (mm == 0.0) {
             if (ci > 0.0) return false;
@@ -247,6 +257,7 @@ ORCA_HD inline bool lp2_plane(const Lane &L, int k, double2 nk, double bk, doubl
         for (int j = -1; j < i; ++j) {
             double ax, ay, cj;
             plane_row(L, j, nk, bk, ax, ay, cj);
+            ORCA_COUNT(plane_inner);
             // a.(c_i m / mm + s d) >= c_j  ->  s (a.d) mm >= c_j mm - c_i (a.m)
             iv.add((ay * mx - ax * my) * mm, cj * mm - ci * (ax * mx + ay * my));
         }
@@ -282,7 +293,9 @@ ORCA_HD inline double lp3_least_penetration(const Lane &L, int m, int start, dou
     for (int k = start; k < m; ++k) {
         const double2 nk = L.N(k);
         const double bk = L.B(k);
+        ORCA_COUNT(lp3_check);
         if (nk.x * vx + nk.y * vy + t >= bk) continue;
+        ORCA_COUNT(lp3_plane);
         double wx, wy;
         if (lp2_plane(L, k, nk, bk, vmax, wx, wy)) {
             vx = wx;

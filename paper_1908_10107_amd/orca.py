@@ -76,6 +76,10 @@ def load(path: str = LIB_PATH):
     L.orca_step.restype = ctypes.c_int
     L.orca_backward.argtypes = [_P, ctypes.c_int32] + [_P] * 7
     L.orca_backward.restype = ctypes.c_int
+    L.orca_step_graph.argtypes = [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_int32]
+    L.orca_step_graph.restype = ctypes.c_int
+    L.orca_autotune.argtypes = [_P, _P, _P, _P, _P, _P, ctypes.c_int32, _P]
+    L.orca_autotune.restype = ctypes.c_int
     L.orca_profile.argtypes = [_P, ctypes.c_int32]
     L.orca_profile.restype = ctypes.c_int
     L.orca_profile_read.argtypes = [_P, _P, _P, _P]
@@ -180,6 +184,27 @@ class Context:
                                        _dev_ptr(pref_vel, "pref_vel", n),
                                        _dev_ptr(goals, "goals", n), int(n_steps),
                                        int(bool(save_tape))))
+
+    def step_graph(self, offsets, params, pos, vel, pref_vel, goals=None, n_steps=1):
+        """orca_step replayed from a captured HIP graph (see orca_step_graph)."""
+        ns, offs, pa, n = self._scene_args(offsets, params)
+        self._sync_stream()
+        self._check(self.lib.orca_step_graph(self.h, ns, offs.ctypes.data_as(_P), pa,
+                                             _dev_ptr(pos, "pos", n), _dev_ptr(vel, "vel", n),
+                                             _dev_ptr(pref_vel, "pref_vel", n),
+                                             _dev_ptr(goals, "goals", n), int(n_steps)))
+
+    def autotune(self, pos, vel, pref_vel=None, goals=None, reps=3):
+        """Pick launch shapes on the current grid; returns (knn_block, fallback_waves_per_cu)."""
+        n = pos.shape[1]
+        scratch = self._torch.empty_like(pos)
+        choice = (ctypes.c_int32 * 2)()
+        self._sync_stream()
+        self._check(self.lib.orca_autotune(self.h, _dev_ptr(pos, "pos", n), _dev_ptr(vel, "vel", n),
+                                           _dev_ptr(pref_vel, "pref_vel", n),
+                                           _dev_ptr(goals, "goals", n), _dev_ptr(scratch, "new_vel", n),
+                                           int(reps), choice))
+        return choice[0], choice[1]
 
     def backward(self, tape_step, g_pos_next, g_vel_next, g_pos, g_vel, g_pref_vel,
                  g_max_speed, g_time_horizon):
