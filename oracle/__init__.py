@@ -220,3 +220,66 @@ def step(pos, vel, pref, offsets, params, goals=None, n_steps=1, radius=None):
                       len(params), _ptr(np.ascontiguousarray(offsets, np.int64)),
                       params_array(params), int(n_steps), _ptr(st))
     return pos, vel, pref, st
+
+
+# ---------------------------------------------------------------- gradients
+
+def _grad_lib():
+    L = lib()
+    if not hasattr(L, "_grad_ready"):
+        L.oracle_traj_loss.argtypes = [I64, P, P, P, I32, P, P, P, P, I32, P]
+        L.oracle_traj_loss.restype = F64
+        L.oracle_traj_jvp.argtypes = [I64, P, P, P, I32, P, P, P, P, I32, P, P, P, P, I32, P, P]
+        L.oracle_traj_jvp.restype = None
+        L.oracle_step_jvp.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P]
+        L.oracle_step_jvp.restype = None
+        L.oracle_choice_jvp.argtypes = [ctypes.c_int] + [P] * 6 + [F64] * 13 + [P]
+        L.oracle_choice_jvp.restype = ctypes.c_int
+        L._grad_ready = True
+    return L
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def traj_loss(pos0, vel0, pref, offsets, params, vmax, tau, n_steps, targets):
+    """L = sum |x(T) - y|^2 after n_steps float64 steps (fixed preferred velocities)."""
+    pos0, vel0, pref, targets, vmax, tau = map(_f64, (pos0, vel0, pref, targets, vmax, tau))
+    n = pos0.shape[1]
+    return _grad_lib().oracle_traj_loss(n, _ptr(pos0), _ptr(vel0), _ptr(pref), len(params),
+                                        _ptr(np.ascontiguousarray(offsets, np.int64)),
+                                        params_array(params), _ptr(vmax), _ptr(tau), int(n_steps),
+                                        _ptr(targets))
+
+
+def traj_jvp(pos0, vel0, pref, offsets, params, vmax, tau, n_steps, targets, dpref, dvmax, dtau,
+             f32_state=False):
+    """(L, dL) with dL the directional derivative along (dpref, dvmax, dtau), complex step.
+
+    f32_state rounds the primal state to float32 after every step.
+    """
+    pos0, vel0, pref, targets, vmax, tau, dpref, dvmax, dtau = map(
+        _f64, (pos0, vel0, pref, targets, vmax, tau, dpref, dvmax, dtau))
+    n = pos0.shape[1]
+    L, dL = ctypes.c_double(), ctypes.c_double()
+    _grad_lib().oracle_traj_jvp(n, _ptr(pos0), _ptr(vel0), _ptr(pref), len(params),
+                                _ptr(np.ascontiguousarray(offsets, np.int64)),
+                                params_array(params), _ptr(vmax), _ptr(tau), int(n_steps),
+                                _ptr(targets), _ptr(dpref), _ptr(dvmax), _ptr(dtau),
+                                int(bool(f32_state)), ctypes.byref(L), ctypes.byref(dL))
+    return L.value, dL.value
+
+
+def step_jvp(pos, vel, pref, offsets, params, dpos, dvel, dpref, dvmax, dtau):
+    """Tangent (dpos', dvel') of one float64 step from the float32 state (complex step)."""
+    pos, vel, pref = map(_f32, (pos, vel, pref))
+    dpos, dvel, dpref, dvmax, dtau = map(_f64, (dpos, dvel, dpref, dvmax, dtau))
+    n = pos.shape[1]
+    op = np.zeros((2, n))
+    ov = np.zeros((2, n))
+    _grad_lib().oracle_step_jvp(n, _ptr(pos), _ptr(vel), _ptr(pref), len(params),
+                                _ptr(np.ascontiguousarray(offsets, np.int64)),
+                                params_array(params), _ptr(dpos), _ptr(dvel), _ptr(dpref),
+                                _ptr(dvmax), _ptr(dtau), _ptr(op), _ptr(ov))
+    return op, ov

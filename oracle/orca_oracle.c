@@ -316,6 +316,41 @@ int oracle_agent_velocity(int64_t n_total, const float *pos, const float *vel, c
                   branch_out);
 }
 
+/*
+ * One agent's choice and its directional derivative (complex step, h =
+ * 1e-30) along tangents of the neighbours' relative positions P [m,2] and
+ * velocities V [m,2], the agent's own velocity, tau, vmax and vhat.  Combined
+ * radii Rs [m] and index order first [m] are fixed.  out: v' (2), dv' (2),
+ * d* (1), dd* (1).  Returns the status (0 projection, 1 fallback).
+ */
+int oracle_choice_jvp(int m, const double *P, const double *dP, const double *V, const double *dV,
+                      const double *Rs, const int *first, double vix, double viy, double dvix,
+                      double dviy, double tau, double dtau, double dt, double vmax, double dvmax,
+                      double vhx, double vhy, double dvhx, double dvhy, double *out)
+{
+    const double h = 1e-30;
+    double complex Px[64], Py[64], Vx[64], Vy[64], Rc[64];
+    halfplane_t_cx hb[64];
+    for (int t = 0; t < m; ++t) {
+        Px[t] = P[2 * t] + I * h * dP[2 * t];
+        Py[t] = P[2 * t + 1] + I * h * dP[2 * t + 1];
+        Vx[t] = V[2 * t] + I * h * dV[2 * t];
+        Vy[t] = V[2 * t + 1] + I * h * dV[2 * t + 1];
+        Rc[t] = Rs[t];
+    }
+    double complex ox, oy, d;
+    int st = choose_cx(m, Px, Py, Vx, Vy, Rc, first, vix + I * h * dvix, viy + I * h * dviy,
+                       tau + I * h * dtau, dt, vmax + I * h * dvmax, vhx + I * h * dvhx,
+                       vhy + I * h * dvhy, &ox, &oy, &d, hb, NULL);
+    out[0] = creal(ox);
+    out[1] = creal(oy);
+    out[2] = cimag(ox) / h;
+    out[3] = cimag(oy) / h;
+    out[4] = creal(d);
+    out[5] = st ? cimag(d) / h : 0.0;
+    return st;
+}
+
 static int scene_of(int32_t n_scenes, const int64_t *off, int64_t i)
 {
     int lo = 0, hi = n_scenes - 1;
@@ -416,4 +451,176 @@ void oracle_step(int64_t n_total, float *pos, float *vel, float *pref, const flo
     }
     free(nv);
     free(vh);
+}
+
+/* ------------------------------------------------------------------ */
+/* Gradients (forward mode by complex step) and float64 trajectories   */
+/* ------------------------------------------------------------------ */
+
+/*
+ * One synchronous step of every agent in REAL arithmetic: fixed preferred
+ * velocities pref, per-scene vmax_s and tau_s (REAL leaves), neighbours from
+ * the binned read of float32(RE(pos)) (the float32 decision the GPU takes).
+ * x <- x + dt v', v <- v'.  Written out for both scalar types below.
+ */
+#define DEFINE_TRAJ_STEP(R_T, SUF, RE_, FIRST_CHOOSE)                                           \
+    static void traj_step##SUF(int64_t n, R_T *pos, R_T *vel, const R_T *pref, int32_t n_scenes,  \
+                               const int64_t *off, const oracle_params *par, const R_T *vmax_s,   \
+                               const R_T *tau_s)                                                  \
+    {                                                                                             \
+        float *p32 = (float *)malloc(sizeof(float) * 2 * (size_t)(n ? n : 1));                   \
+        R_T *nv = (R_T *)malloc(sizeof(R_T) * 2 * (size_t)(n ? n : 1));                           \
+        for (int64_t i = 0; i < 2 * n; ++i) p32[i] = (float)RE_(pos[i]);                          \
+        bins_t *bins = (bins_t *)calloc((size_t)n_scenes, sizeof(bins_t));                        \
+        for (int s = 0; s < n_scenes; ++s)                                                        \
+            bins_build(&bins[s], n, p32, off[s], off[s + 1], par[s].neighbor_dist);               \
+        _Pragma("omp parallel for schedule(dynamic, 16)")                                         \
+        for (int64_t i = 0; i < n; ++i) {                                                         \
+            int s = scene_of(n_scenes, off, i);                                                   \
+            const oracle_params *p = &par[s];                                                     \
+            int64_t ids[64];                                                                      \
+            int32_t m = knn_binned(&bins[s], n, p32, i, p->neighbor_dist, p->max_neighbors, ids,  \
+                                   NULL);                                                         \
+            R_T Px[64], Py[64], Vx[64], Vy[64], Rs[64];                                           \
+            int first[64];                                                                        \
+            for (int32_t t = 0; t < m; ++t) {                                                     \
+                int64_t j = ids[t];                                                               \
+                Px[t] = pos[j] - pos[i];                                                          \
+                Py[t] = pos[n + j] - pos[n + i];                                                  \
+                Vx[t] = vel[i] - vel[j];                                                          \
+                Vy[t] = vel[n + i] - vel[n + j];                                                  \
+                Rs[t] = 2.0 * (double)p->radius;                                                  \
+                first[t] = i < j;                                                                 \
+            }                                                                                     \
+            FIRST_CHOOSE;                                                                         \
+        }                                                                                         \
+        for (int64_t i = 0; i < n; ++i) {                                                         \
+            double dt = par[scene_of(n_scenes, off, i)].dt;                                       \
+            pos[i] = pos[i] + dt * nv[2 * i];                                                     \
+            pos[n + i] = pos[n + i] + dt * nv[2 * i + 1];                                         \
+            vel[i] = nv[2 * i];                                                                   \
+            vel[n + i] = nv[2 * i + 1];                                                           \
+        }                                                                                         \
+        for (int s = 0; s < n_scenes; ++s) bins_free(&bins[s]);                                   \
+        free(bins);                                                                               \
+        free(nv);                                                                                 \
+        free(p32);                                                                                \
+    }
+
+DEFINE_TRAJ_STEP(double, _d, (double), {
+    halfplane hb[64];
+    choose(m, Px, Py, Vx, Vy, Rs, first, vel[i], vel[n + i], tau_s[s], p->dt, vmax_s[s], pref[i],
+           pref[n + i], &nv[2 * i], &nv[2 * i + 1], NULL, hb, NULL);
+})
+
+DEFINE_TRAJ_STEP(double complex, _c, creal, {
+    halfplane_t_cx hb[64];
+    choose_cx(m, Px, Py, Vx, Vy, Rs, first, vel[i], vel[n + i], tau_s[s], p->dt, vmax_s[s],
+              pref[i], pref[n + i], &nv[2 * i], &nv[2 * i + 1], NULL, hb, NULL);
+})
+
+/*
+ * Loss L = sum_i |x_i(T) - y_i|^2 after n_steps float64 steps from
+ * (pos0, vel0) with fixed preferred velocities pref and per-scene vmax_s,
+ * tau_s.  Used for central finite differences.
+ */
+double oracle_traj_loss(int64_t n, const double *pos0, const double *vel0, const double *pref,
+                        int32_t n_scenes, const int64_t *off, const oracle_params *par,
+                        const double *vmax_s, const double *tau_s, int32_t n_steps,
+                        const double *targets)
+{
+    double *pos = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    double *vel = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    memcpy(pos, pos0, sizeof(double) * 2 * (size_t)n);
+    memcpy(vel, vel0, sizeof(double) * 2 * (size_t)n);
+    for (int32_t t = 0; t < n_steps; ++t)
+        traj_step_d(n, pos, vel, pref, n_scenes, off, par, vmax_s, tau_s);
+    double L = 0.0;
+    for (int64_t i = 0; i < 2 * n; ++i) L += (pos[i] - targets[i]) * (pos[i] - targets[i]);
+    free(pos);
+    free(vel);
+    return L;
+}
+
+/*
+ * The same loss and its directional derivative along (dpref, dvmax, dtau) by
+ * complex step (h = 1e-30): the discrete choices are those of the primal.
+ * With f32_state the primal state is rounded to float32 after every step
+ * (the tangent is not), which is the trajectory a float32-state step takes.
+ */
+void oracle_traj_jvp(int64_t n, const double *pos0, const double *vel0, const double *pref,
+                     int32_t n_scenes, const int64_t *off, const oracle_params *par,
+                     const double *vmax_s, const double *tau_s, int32_t n_steps,
+                     const double *targets, const double *dpref, const double *dvmax,
+                     const double *dtau, int32_t f32_state, double *loss, double *dloss)
+{
+    const double h = 1e-30;
+    double complex *pos = (double complex *)malloc(sizeof(double complex) * 2 * (size_t)n);
+    double complex *vel = (double complex *)malloc(sizeof(double complex) * 2 * (size_t)n);
+    double complex *pr = (double complex *)malloc(sizeof(double complex) * 2 * (size_t)n);
+    double complex *vm = (double complex *)malloc(sizeof(double complex) * (size_t)n_scenes);
+    double complex *ta = (double complex *)malloc(sizeof(double complex) * (size_t)n_scenes);
+    for (int64_t i = 0; i < 2 * n; ++i) {
+        pos[i] = pos0[i];
+        vel[i] = vel0[i];
+        pr[i] = pref[i] + I * h * (dpref ? dpref[i] : 0.0);
+    }
+    for (int s = 0; s < n_scenes; ++s) {
+        vm[s] = vmax_s[s] + I * h * (dvmax ? dvmax[s] : 0.0);
+        ta[s] = tau_s[s] + I * h * (dtau ? dtau[s] : 0.0);
+    }
+    for (int32_t t = 0; t < n_steps; ++t) {
+        traj_step_c(n, pos, vel, pr, n_scenes, off, par, vm, ta);
+        if (f32_state) /* keep the primal on float32 states (as the GPU stores them) */
+            for (int64_t i = 0; i < 2 * n; ++i) {
+                pos[i] = (double)(float)creal(pos[i]) + I * cimag(pos[i]);
+                vel[i] = (double)(float)creal(vel[i]) + I * cimag(vel[i]);
+            }
+    }
+    double complex L = 0.0;
+    for (int64_t i = 0; i < 2 * n; ++i) L += (pos[i] - targets[i]) * (pos[i] - targets[i]);
+    *loss = creal(L);
+    *dloss = cimag(L) / h;
+    free(pos);
+    free(vel);
+    free(pr);
+    free(vm);
+    free(ta);
+}
+
+/*
+ * Tangent of one step from a float32 state along (dpos, dvel, dpref, dvmax,
+ * dtau): dpos_out, dvel_out [2, n] (complex step).  The step is the float64
+ * map x' = x + dt v', v' (no float32 rounding of the result).
+ */
+void oracle_step_jvp(int64_t n, const float *pos, const float *vel, const float *pref,
+                     int32_t n_scenes, const int64_t *off, const oracle_params *par,
+                     const double *dpos, const double *dvel, const double *dpref,
+                     const double *dvmax, const double *dtau, double *dpos_out, double *dvel_out)
+{
+    const double h = 1e-30;
+    double complex *p = (double complex *)malloc(sizeof(double complex) * 2 * (size_t)n);
+    double complex *v = (double complex *)malloc(sizeof(double complex) * 2 * (size_t)n);
+    double complex *pr = (double complex *)malloc(sizeof(double complex) * 2 * (size_t)n);
+    double complex *vm = (double complex *)malloc(sizeof(double complex) * (size_t)n_scenes);
+    double complex *ta = (double complex *)malloc(sizeof(double complex) * (size_t)n_scenes);
+    for (int64_t i = 0; i < 2 * n; ++i) {
+        p[i] = (double)pos[i] + I * h * dpos[i];
+        v[i] = (double)vel[i] + I * h * dvel[i];
+        pr[i] = (double)pref[i] + I * h * dpref[i];
+    }
+    for (int s = 0; s < n_scenes; ++s) {
+        vm[s] = (double)par[s].max_speed + I * h * dvmax[s];
+        ta[s] = (double)par[s].time_horizon + I * h * dtau[s];
+    }
+    traj_step_c(n, p, v, pr, n_scenes, off, par, vm, ta);
+    for (int64_t i = 0; i < 2 * n; ++i) {
+        dpos_out[i] = cimag(p[i]) / h;
+        dvel_out[i] = cimag(v[i]) / h;
+    }
+    free(p);
+    free(v);
+    free(pr);
+    free(vm);
+    free(ta);
 }

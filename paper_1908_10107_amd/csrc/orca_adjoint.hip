@@ -1,0 +1,141 @@
+// orca_adjoint.hip -- adjoint (vector-Jacobian product) of one recorded step.
+//
+// The step is x' = x + dt v', v_next = v', with v' the velocity choice of
+// section 3 made from the state at the step's start.  Given dL/dx' and
+// dL/dv_next, k_backward handles each agent i:
+//   g = dL/dv'_i = dL/dv_next_i + dt dL/dx'_i;
+//   refetch from the tape the (at most five) half-planes that fix v'_i
+//   (orca_adjoint.h), push g back through the programs to those half-planes,
+//   to vhat_i and to v_max, then through each half-plane to its relative
+//   position P = x_j - x_i, relative velocity V = v_i - v_j, v_i (through
+//   v_i + u/2) and tau;
+//   scatter P and V gradients to agents i and j with float64 atomics.
+// k_backward_finish then writes dL/dx = dL/dx' + (scattered part), dL/dv
+// (scattered part), adds the per-scene v_max and tau gradients, and clears
+// the float64 accumulators for the next use.
+#include <hip/hip_runtime.h>
+
+#include "orca_internal.h"
+
+namespace orca {
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_backward(BackArgs a)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t n = a.n;
+    const bool live = i < n;
+    int32_t sc = 0;
+    double gvmax = 0.0, gtau = 0.0;
+    if (live) {
+        sc = a.agent_scene[i];
+        const SceneDev p = a.sp[sc];
+        const TapeCode tc = a.codes[i];
+        const float4 me = a.state[i];
+        const double R = 2.0 * (double)p.radius, tau = (double)p.tau, dt = (double)p.dt;
+        const double vmax = (double)p.vmax;
+        const double vix = (double)me.z, viy = (double)me.w;
+        const double vhx = (double)a.pref[i], vhy = (double)a.pref[n + i];
+        const double gx = (double)a.g_vel_next[i] + dt * (double)a.g_pos_next[i];
+        const double gy = (double)a.g_vel_next[n + i] + dt * (double)a.g_pos_next[n + i];
+        int r[kSlots];
+        slot_rows(tc, r);
+        RowGeom rows[kSlots];
+        int32_t js[kSlots];
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) {
+            js[q] = -1;
+            rows[q] = RowGeom{};
+            if (r[q] >= 0) {
+                const int32_t j = a.nbr[(int64_t)i * a.krow + r[q]];
+                const float4 o = a.state[j];
+                rows[q].Px = (double)o.x - (double)me.x;
+                rows[q].Py = (double)o.y - (double)me.y;
+                rows[q].Vx = vix - (double)o.z;
+                rows[q].Vy = viy - (double)o.w;
+                rows[q].first = i < j;
+                row_geom(rows[q], R, tau, dt, vix, viy);
+                js[q] = j;
+            }
+        }
+        SlotGrads sg;
+        sg.clear();
+        double gvhx = 0.0, gvhy = 0.0;
+        choice_vjp(rows, tc, vmax, vhx, vhy, gx, gy, sg, gvhx, gvhy, gvmax);
+        double gvix = 0.0, gviy = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) {
+            if (js[q] < 0) continue;
+            double gPx = 0.0, gPy = 0.0, gVx = 0.0, gVy = 0.0;
+            row_vjp(rows[q], R, tau, dt, vix, viy, sg.gnx[q], sg.gny[q], sg.gb[q], gPx, gPy, gVx,
+                    gVy, gtau, gvix, gviy);
+            const int32_t j = js[q];
+            // P = x_j - x_i, V = v_i - v_j
+            atomicAdd(&a.acc[j], gPx);
+            atomicAdd(&a.acc[n + j], gPy);
+            atomicAdd(&a.acc[i], -gPx);
+            atomicAdd(&a.acc[n + i], -gPy);
+            atomicAdd(&a.acc[2 * n + j], -gVx);
+            atomicAdd(&a.acc[3 * n + j], -gVy);
+            gvix += gVx;
+            gviy += gVy;
+        }
+        atomicAdd(&a.acc[2 * n + i], gvix);
+        atomicAdd(&a.acc[3 * n + i], gviy);
+        a.g_pref[i] += (float)gvhx;
+        a.g_pref[n + i] += (float)gvhy;
+    }
+    // per-scene parameters: one atomic per wave when the wave is one scene
+    const int32_t sc0 = __shfl(sc, 0, 64);
+    const uint64_t same = __ballot(!live || sc == sc0);
+    if (same == ~0ull) {
+        const double sv = wave_sum_f64(gvmax), st = wave_sum_f64(gtau);
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd(&a.acc_scene[sc0], sv);
+            atomicAdd(&a.acc_scene[a.n_scenes + sc0], st);
+        }
+    } else if (live) {
+        atomicAdd(&a.acc_scene[sc], gvmax);
+        atomicAdd(&a.acc_scene[a.n_scenes + sc], gtau);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_backward_finish(BackArgs a)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t n = a.n;
+    if (i < n) {
+        const double gx = (double)a.g_pos_next[i] + a.acc[i];
+        const double gy = (double)a.g_pos_next[n + i] + a.acc[n + i];
+        a.g_pos[i] = (float)gx;
+        a.g_pos[n + i] = (float)gy;
+        a.g_vel[i] = (float)a.acc[2 * n + i];
+        a.g_vel[n + i] = (float)a.acc[3 * n + i];
+        a.acc[i] = 0.0;
+        a.acc[n + i] = 0.0;
+        a.acc[2 * n + i] = 0.0;
+        a.acc[3 * n + i] = 0.0;
+    }
+    if (i < a.n_scenes) {
+        if (a.g_max_speed) a.g_max_speed[i] += (float)a.acc_scene[i];
+        if (a.g_time_horizon) a.g_time_horizon[i] += (float)a.acc_scene[a.n_scenes + i];
+        a.acc_scene[i] = 0.0;
+        a.acc_scene[a.n_scenes + i] = 0.0;
+    }
+}
+
+hipError_t launch_backward(const BackArgs &a, hipStream_t st)
+{
+    if (a.n > 0)
+        hipLaunchKernelGGL(k_backward, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+    const int32_t m = a.n > a.n_scenes ? a.n : a.n_scenes;
+    if (m > 0) hipLaunchKernelGGL(k_backward_finish, dim3((m + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace orca

@@ -67,6 +67,16 @@ struct orca_ctx {
     double stage_ms[ORCA_PROF_STAGES] = {0};
     int64_t prof_steps = 0, prof_fallback = 0;
 
+    // tape of recorded steps for orca_backward
+    float4 *tape_state = nullptr;           // [tape_steps, A]
+    int32_t *tape_nbr = nullptr;            // [tape_steps, A, k_max]
+    orca::TapeCode *tape_codes = nullptr;   // [tape_steps, A]
+    double *acc = nullptr;                  // [4, A]
+    double *acc_scene = nullptr;            // [2, S]
+    int32_t tape_len = 0;                   // steps held by the last recording
+    uint64_t tape_scene_version = 0;
+    const float *tape_pref = nullptr;
+
     // launch shapes (orca_autotune picks them)
     int32_t knn_block = 256, fb_waves_per_cu = 16;
 
@@ -358,7 +368,14 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->ncount, sizeof(int32_t) * A) &&
               alloc((void **)&ctx->fb_list, sizeof(orca::FallbackItem) * A) &&
               alloc((void **)&ctx->stash_n, sizeof(double2) * A * (size_t)k_max) &&
-              alloc((void **)&ctx->stash_b, sizeof(double) * A * (size_t)k_max);
+              alloc((void **)&ctx->stash_b, sizeof(double) * A * (size_t)k_max) &&
+              alloc((void **)&ctx->acc, sizeof(double) * 4 * A) &&
+              alloc((void **)&ctx->acc_scene, sizeof(double) * 2 * S);
+    const size_t T = (size_t)tape_steps;
+    if (ok && T > 0)
+        ok = alloc((void **)&ctx->tape_state, sizeof(float4) * T * A) &&
+             alloc((void **)&ctx->tape_nbr, sizeof(int32_t) * T * A * (size_t)k_max) &&
+             alloc((void **)&ctx->tape_codes, sizeof(orca::TapeCode) * T * A);
     if (!ok) {
         free_all(ctx);
         delete ctx;
@@ -367,6 +384,8 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
     // counts start at zero and are kept zero between uses by the scan
     hipError_t e = hipMemsetAsync(ctx->counts, 0, sizeof(int32_t) * C, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->counters, 0, sizeof(Counters), ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->acc, 0, sizeof(double) * 4 * A, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->acc_scene, 0, sizeof(double) * 2 * S, ctx->stream);
     if (e == hipSuccess) e = orca::launch_scene_map(ctx->off, max_scenes, ctx->agent_scene, 0,
                                                     ctx->bbox, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -444,7 +463,6 @@ int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
         if (n_steps > ctx->tape_steps)
             return fail(ctx, ORCA_ECAPACITY, "n_steps %d exceeds tape_steps %d", n_steps,
                         ctx->tape_steps);
-        return fail(ctx, ORCA_ESTATE, "step recording is not available in this build");
     }
     orca::Plan pl = make_plan(ctx);
     pl.out.pos = pos;
@@ -452,9 +470,22 @@ int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
     pl.out.pref = pref_vel;
     pl.out.goals = goals;
     ctx->grid_valid = false;
+    if (save_tape) ctx->tape_len = 0;
     for (int32_t t = 0; t < n_steps; ++t) {
+        if (save_tape) {
+            const size_t A = (size_t)ctx->max_agents;
+            pl.out.tape_state = ctx->tape_state + (size_t)t * A;
+            pl.out.tape_codes = ctx->tape_codes + (size_t)t * A;
+            pl.out.nbr_out = ctx->tape_nbr + (size_t)t * A * (size_t)ctx->k_max;
+            pl.out.krow = ctx->k_max;
+        }
         rc = run_pass(ctx, pl, pos, vel);
         if (rc != ORCA_OK) return rc;
+    }
+    if (save_tape) {
+        ctx->tape_len = n_steps;
+        ctx->tape_scene_version = ctx->scene_version;
+        ctx->tape_pref = pref_vel;
     }
     return ORCA_OK;
 }
@@ -584,15 +615,35 @@ int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
                   float *g_max_speed, float *g_time_horizon)
 {
     if (!ctx) return ORCA_EINVAL;
-    (void)tape_step;
-    (void)g_pos_next;
-    (void)g_vel_next;
-    (void)g_pos;
-    (void)g_vel;
-    (void)g_pref_vel;
-    (void)g_max_speed;
-    (void)g_time_horizon;
-    return fail(ctx, ORCA_ESTATE, "no recorded step: step recording is not available in this build");
+    if (tape_step < 0 || tape_step >= ctx->tape_len)
+        return fail(ctx, ORCA_ESTATE, "no recorded step %d (the last recording holds %d)",
+                    tape_step, ctx->tape_len);
+    if (ctx->tape_scene_version != ctx->scene_version)
+        return fail(ctx, ORCA_ESTATE, "the scene set changed since the steps were recorded");
+    if (ctx->n > 0 && (!g_pos_next || !g_vel_next || !g_pos || !g_vel || !g_pref_vel))
+        return fail(ctx, ORCA_EINVAL, "gradient arrays must be non-NULL");
+    const size_t A = (size_t)ctx->max_agents;
+    orca::BackArgs a{};
+    a.n = (int32_t)ctx->n;
+    a.n_scenes = ctx->n_scenes;
+    a.krow = ctx->k_max;
+    a.agent_scene = ctx->agent_scene;
+    a.sp = ctx->sp;
+    a.state = ctx->tape_state + (size_t)tape_step * A;
+    a.nbr = ctx->tape_nbr + (size_t)tape_step * A * (size_t)ctx->k_max;
+    a.codes = ctx->tape_codes + (size_t)tape_step * A;
+    a.pref = ctx->tape_pref;
+    a.g_pos_next = g_pos_next;
+    a.g_vel_next = g_vel_next;
+    a.g_pos = g_pos;
+    a.g_vel = g_vel;
+    a.g_pref = g_pref_vel;
+    a.g_max_speed = g_max_speed;
+    a.g_time_horizon = g_time_horizon;
+    a.acc = ctx->acc;
+    a.acc_scene = ctx->acc_scene;
+    HIP_OK(orca::launch_backward(a, ctx->stream));
+    return ORCA_OK;
 }
 
 }  // extern "C"

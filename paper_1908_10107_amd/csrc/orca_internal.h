@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "orca_adjoint.h"
+
 namespace orca {
 
 constexpr int kScanItems = 16;
@@ -11,7 +13,6 @@ constexpr int kScanBlock = 256;
 constexpr int kScanTile = kScanItems * kScanBlock;  // cells per scan tile
 constexpr int kLpBlock = 64;                        // one wave per LP block
 constexpr int kBboxChunk = 8192;                    // agents per bounding-box block
-constexpr double kDelta = 1e-5;  // relaxation of the least-penetration second stage (m/s)
 constexpr double kCellMargin = 1.0 + 1.0 / 1024.0;  // cell side / neighbor_dist
 
 // Per-scene parameters as the kernels read them.
@@ -53,6 +54,8 @@ struct OutArgs {
     uint8_t *status;     // [N] or nullptr
     int32_t *nbr_out;    // [N, krow] or nullptr
     int32_t krow;
+    float4 *tape_state;  // recorded step: state (x, y, vx, vy) at the step's start, or nullptr
+    TapeCode *tape_codes;  // recorded step: how each velocity was chosen
 };
 
 // Device buffers and sizes of one launch sequence.
@@ -86,5 +89,21 @@ hipError_t launch_fill_vel(const Plan &pl, const float *vel, hipStream_t st);
 hipError_t launch_knn(const Plan &pl, int kmax, hipStream_t st);
 hipError_t launch_lp(const Plan &pl, int kmax, hipStream_t st);
 hipError_t launch_fallback(const Plan &pl, int kmax, hipStream_t st);
+
+// Adjoint of one recorded step (orca_adjoint.hip).
+struct BackArgs {
+    int32_t n, n_scenes, krow;
+    const int32_t *agent_scene;
+    const SceneDev *sp;
+    const float4 *state;      // tape: state at the step's start
+    const int32_t *nbr;       // tape: neighbour ids [n, krow]
+    const TapeCode *codes;    // tape: choices
+    const float *pref;        // fixed preferred velocities [2, n]
+    const float *g_pos_next, *g_vel_next;
+    float *g_pos, *g_vel, *g_pref, *g_max_speed, *g_time_horizon;
+    double *acc;              // [4, n] float64 accumulators (kept zero between uses)
+    double *acc_scene;        // [2, n_scenes]
+};
+hipError_t launch_backward(const BackArgs &a, hipStream_t st);
 
 }  // namespace orca

@@ -532,7 +532,7 @@ __device__ __forceinline__ void write_result(const OutArgs &o, float mex, float 
 // whose projection is empty is handed to the fallback list with everything
 // k_fallback needs (one atomic per wave), and its half-planes go to column
 // `slot` of the stash.
-template <int KMAX>
+template <int KMAX, bool REC>
 __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sorted,
                                                  const int32_t *__restrict__ sid,
                                                  const int32_t *__restrict__ agent_scene,
@@ -561,9 +561,21 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
         disc_clip(vmax, vhx, vhy, vx, vy);
         const int m = build_constraints(L, s, id, me, p, sorted, sid, nbr, ld, ncount,
                                         out.nbr_out, out.krow);
-        const int fail = lp2_project(L, m, 0, 0.0, vmax, vhx, vhy, vx, vy);
+        Active act;
+        const int fail = lp2_project<REC>(L, m, 0, 0.0, vmax, vhx, vhy, vx, vy, &act);
+        if (REC) out.tape_state[id] = me;
         if (fail < 0) {
             write_result(out, me.x, me.y, p.dt, id, n, vx, vy, vhx, vhy, 0);
+            if (REC) {
+                TapeCode tc{};
+                tc.status = 0;
+                tc.p_line = (int8_t)act.line;
+                tc.p_src = (int8_t)act.src;
+                tc.d_plane = -1;
+                tc.d_line = (int8_t)kLineNone;
+                tc.d_src = (int8_t)kSrcDisc;
+                out.tape_codes[id] = tc;
+            }
         } else {
             need_fb = true;
             it.s = s;
@@ -604,7 +616,7 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
 // the least penetration d* from the projection's last optimum (the rows
 // before the failed one are satisfied there with t = 0), then take the point
 // closest to vhat among those within d* + delta of every half-plane.
-template <int KMAX>
+template <int KMAX, bool REC>
 __global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, int32_t ld,
                                                        const FallbackItem *__restrict__ fb_list,
                                                        const double2 *__restrict__ stash_n,
@@ -625,12 +637,28 @@ __global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, i
         }
         const double vmax = (double)it.vmax;
         double vx = it.vx, vy = it.vy;
-        const double d = lp3_least_penetration(L, m, it.fail, vmax, vx, vy);
+        int plane = -1;
+        Active dact, ract;
+        const double d = lp3_least_penetration<REC>(L, m, it.fail, vmax, vx, vy, &plane, &dact);
         double wx, wy;
         disc_clip(vmax, it.vhx, it.vhy, wx, wy);
-        if (lp2_project(L, m, 0, d + kDelta, vmax, it.vhx, it.vhy, wx, wy) < 0) {
+        const bool ok =
+            lp2_project<REC>(L, m, 0, d + kRelax, vmax, it.vhx, it.vhy, wx, wy, &ract) < 0;
+        if (ok) {
             vx = wx;
             vy = wy;
+        }
+        if (REC) {
+            TapeCode tc{};
+            tc.status = 1;
+            tc.p_line = (int8_t)ract.line;
+            tc.p_src = (int8_t)ract.src;
+            tc.d_plane = (int8_t)plane;
+            tc.d_line = (int8_t)dact.line;
+            tc.d_src = (int8_t)dact.src;
+            tc.relaxed_empty = ok ? 0 : 1;
+            tc.dstar = d;
+            out.tape_codes[it.id] = tc;
         }
         write_result(out, it.mex, it.mey, it.dt, it.id, n, vx, vy, it.vhx, it.vhy, 1);
     }
@@ -649,25 +677,40 @@ hipError_t launch_knn_k(const Plan &pl, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int KMAX>
-hipError_t launch_lp_k(const Plan &pl, hipStream_t st)
+template <int KMAX, bool REC>
+hipError_t launch_lp_rec(const Plan &pl, hipStream_t st)
 {
     const int32_t n = pl.n;
     const int32_t gl = (n + kLpBlock - 1) / kLpBlock;
-    hipLaunchKernelGGL(k_lp<KMAX>, dim3(gl), dim3(kLpBlock), 0, st, pl.sorted, pl.sid,
+    hipLaunchKernelGGL((k_lp<KMAX, REC>), dim3(gl), dim3(kLpBlock), 0, st, pl.sorted, pl.sid,
                        pl.agent_scene, pl.sp, n, pl.nbr, pl.ld, pl.ncount, pl.out, pl.fb_list,
                        pl.stash_n, pl.stash_b, pl.counters);
     return hipGetLastError();
 }
 
-template <int KMAX>
-hipError_t launch_fallback_k(const Plan &pl, hipStream_t st)
+template <int KMAX, bool REC>
+hipError_t launch_fallback_rec(const Plan &pl, hipStream_t st)
 {
     // persistent: fb_waves_per_cu one-wave blocks per CU loop over the device-side list
     const int32_t gf = max(1, min((pl.n + kLpBlock - 1) / kLpBlock, pl.fb_waves_per_cu * pl.cus));
-    hipLaunchKernelGGL(k_fallback<KMAX>, dim3(gf), dim3(kLpBlock), 0, st, pl.out, pl.n, pl.ld,
+    hipLaunchKernelGGL((k_fallback<KMAX, REC>), dim3(gf), dim3(kLpBlock), 0, st, pl.out, pl.n, pl.ld,
                        pl.fb_list, pl.stash_n, pl.stash_b, pl.counters);
     return hipGetLastError();
+}
+
+// Recording (for the adjoint) is a separate instantiation: the plain one
+// carries none of its bookkeeping.
+template <int KMAX>
+hipError_t launch_lp_k(const Plan &pl, hipStream_t st)
+{
+    return pl.out.tape_codes ? launch_lp_rec<KMAX, true>(pl, st) : launch_lp_rec<KMAX, false>(pl, st);
+}
+
+template <int KMAX>
+hipError_t launch_fallback_k(const Plan &pl, hipStream_t st)
+{
+    return pl.out.tape_codes ? launch_fallback_rec<KMAX, true>(pl, st)
+                             : launch_fallback_rec<KMAX, false>(pl, st);
 }
 
 // The neighbour-list length picks the register / LDS footprint.

@@ -110,11 +110,26 @@ struct Lane {
     ORCA_HD inline double B(int k) const { return b[k * kLpStride]; }
 };
 
+// What fixes the final point of an incremental 2D program (kept when a step
+// is recorded for the adjoint): the row whose 1D program ran last (line; -1:
+// none ran, the start point stands) and what bounds the point on that line
+// (src: a row index, kSrcDisc, or kSrcFree when the line's own optimum lies
+// inside its interval).  Row -1 of a plane program is "t >= 0".
+constexpr int kSrcDisc = -2;
+constexpr int kSrcFree = -3;
+constexpr int kLineNone = -4;    // Active.line when no 1D program ran
+constexpr double kRelax = 1e-5;  // relaxation of the least-penetration second stage (m/s)
+struct Active {
+    int line, src;
+};
+
 // Feasible interval lo <= s <= hi of a 1D program, each end kept as a
 // fraction with a positive denominator and compared by cross-multiplication,
-// so adding a constraint costs no division.
+// so adding a constraint costs no division.  lo_src / hi_src name the row
+// that set each end (kSrcDisc for the disc).
 struct Interval {
     double lo_n, lo_d, hi_n, hi_d;
+    int lo_src, hi_src;
     bool bad;
     ORCA_HD inline void init(double h_n, double h_d)
     {
@@ -122,34 +137,42 @@ struct Interval {
         lo_d = h_d;
         hi_n = h_n;
         hi_d = h_d;
+        lo_src = kSrcDisc;
+        hi_src = kSrcDisc;
         bad = false;
     }
-    // add s * den >= num
-    ORCA_HD inline void add(double den, double num)
+    // add s * den >= num (row src)
+    ORCA_HD inline void add(double den, double num, int src)
     {
         const bool up = den > 0.0, down = den < 0.0;
         const bool raise = up && num * lo_d > lo_n * den;
         const bool lower = down && num * hi_d > hi_n * den;  // num/den < hi, den < 0
         lo_n = raise ? num : lo_n;
         lo_d = raise ? den : lo_d;
+        lo_src = raise ? src : lo_src;
         hi_n = lower ? -num : hi_n;
         hi_d = lower ? -den : hi_d;
+        hi_src = lower ? src : hi_src;
         bad = bad | (!up & !down & (num > 0.0));
     }
     ORCA_HD inline bool empty() const { return bad || lo_n * hi_d > hi_n * lo_d; }
-    // t clamped into the interval, as a fraction (t_n / t_d)
-    ORCA_HD inline void clamp(double t, double &t_n, double &t_d) const
+    // t_n / t_d clamped into the interval (t_d > 0); returns the source that
+    // bounds the result (kSrcFree if t was inside)
+    ORCA_HD inline int clamp(double t_n, double t_d, double &o_n, double &o_d) const
     {
-        if (t * lo_d < lo_n) {
-            t_n = lo_n;
-            t_d = lo_d;
-        } else if (t * hi_d > hi_n) {
-            t_n = hi_n;
-            t_d = hi_d;
-        } else {
-            t_n = t;
-            t_d = 1.0;
+        if (t_n * lo_d < lo_n * t_d) {
+            o_n = lo_n;
+            o_d = lo_d;
+            return lo_src;
         }
+        if (t_n * hi_d > hi_n * t_d) {
+            o_n = hi_n;
+            o_d = hi_d;
+            return hi_src;
+        }
+        o_n = t_n;
+        o_d = t_d;
+        return kSrcFree;
     }
 };
 
@@ -159,11 +182,16 @@ struct Interval {
 // violates constraint k the new optimum lies on its line, found by a 1D
 // program against the disc and constraints 0..k-1.  Returns -1 (feasible, v
 // set) or the first k whose 1D program is empty (v = the optimum over
-// constraints 0..k-1).
-ORCA_HD inline int lp2_project(const Lane &L, int m, int from, double relax, double vmax, double vhx,
-                           double vhy, double &vx, double &vy)
+// constraints 0..k-1).  With REC the last line and its bound go to *act.
+template <bool REC>
+ORCA_HD inline int lp2_project(const Lane &L, int m, int from, double relax, double vmax,
+                               double vhx, double vhy, double &vx, double &vy, Active *act)
 {
     const double vm2 = vmax * vmax;
+    if (REC) {
+        act->line = kLineNone;
+        act->src = kSrcFree;
+    }
     for (int k = from; k < m; ++k) {
         const double2 nk = L.N(k);
         const double bk = L.B(k) - relax;
@@ -182,21 +210,24 @@ ORCA_HD inline int lp2_project(const Lane &L, int m, int from, double relax, dou
             const double2 nj = L.N(j);
             const double bj = L.B(j) - relax;
             ORCA_COUNT(lp2_inner);
-            iv.add(nj.y * nk.x - nj.x * nk.y, bj - bk * (nj.x * nk.x + nj.y * nk.y));
+            iv.add(nj.y * nk.x - nj.x * nk.y, bj - bk * (nj.x * nk.x + nj.y * nk.y), j);
         }
         if (iv.empty()) return k;
         double tn, td;
-        iv.clamp(nk.x * vhy - nk.y * vhx, tn, td);  // d_k . vhat, clamped
+        const int src = iv.clamp(nk.x * vhy - nk.y * vhx, 1.0, tn, td);  // d_k . vhat, clamped
         const double t = tn / td;
         vx = bk * nk.x - t * nk.y;
         vy = bk * nk.y + t * nk.x;
+        if (REC) {
+            act->line = k;
+            act->src = src;
+        }
     }
     return -1;
 }
 
 // Start of lp2_project: vhat, pulled radially into the disc.
-ORCA_HD inline void disc_clip(double vmax, double vhx, double vhy, double &vx,
-                                          double &vy)
+ORCA_HD inline void disc_clip(double vmax, double vhx, double vhy, double &vx, double &vy)
 {
     const double vh2 = vhx * vhx + vhy * vhy;
     if (vh2 > vmax * vmax) {
@@ -213,7 +244,7 @@ ORCA_HD inline void disc_clip(double vmax, double vhx, double vhy, double &vx,
 // penetration" (-n_k . v >= -b_k), i >= 0 is "constraint i penetrates no more
 // than k" ((n_i - n_k) . v >= b_i - b_k).
 ORCA_HD inline void plane_row(const Lane &L, int i, double2 nk, double bk, double &mx,
-                                          double &my, double &c)
+                              double &my, double &c)
 {
     if (i < 0) {
         mx = -nk.x;
@@ -231,13 +262,19 @@ ORCA_HD inline void plane_row(const Lane &L, int i, double2 nk, double bk, doubl
 // (incremental, as lp2_project but with a linear objective).  Line i is
 // p(s) = c_i m_i / |m_i|^2 + s (-m_i.y, m_i.x); each constraint j on it is
 // multiplied through by |m_i|^2 > 0 so no division is needed until the end.
-// Returns false if the subproblem is empty.
-ORCA_HD inline bool lp2_plane(const Lane &L, int k, double2 nk, double bk, double vmax, double &vx,
-                          double &vy)
+// Returns false if the subproblem is empty.  With REC the last line and its
+// bound go to *act (line kLineNone: the start point vmax n_k stands).
+template <bool REC>
+ORCA_HD inline bool lp2_plane(const Lane &L, int k, double2 nk, double bk, double vmax,
+                              double &vx, double &vy, Active *act)
 {
     const double vm2 = vmax * vmax;
     vx = vmax * nk.x;
     vy = vmax * nk.y;
+    if (REC) {
+        act->line = kLineNone;
+        act->src = kSrcDisc;
+    }
     for (int i = -1; i < k; ++i) {
         double mx, my, ci;
         plane_row(L, i, nk, bk, mx, my, ci);
@@ -259,24 +296,31 @@ ORCA_HD inline bool lp2_plane(const Lane &L, int k, double2 nk, double bk, doubl
             plane_row(L, j, nk, bk, ax, ay, cj);
             ORCA_COUNT(plane_inner);
             // a.(c_i m / mm + s d) >= c_j  ->  s (a.d) mm >= c_j mm - c_i (a.m)
-            iv.add((ay * mx - ax * my) * mm, cj * mm - ci * (ax * mx + ay * my));
+            iv.add((ay * mx - ax * my) * mm, cj * mm - ci * (ax * mx + ay * my), j);
         }
         if (iv.empty()) return false;
         const double slope = nk.y * mx - nk.x * my;  // n_k . (-my, mx)
         double sn, sd;
+        int src;
         if (slope > 0.0) {
             sn = iv.hi_n;
             sd = iv.hi_d;
+            src = iv.hi_src;
         } else if (slope < 0.0) {
             sn = iv.lo_n;
             sd = iv.lo_d;
+            src = iv.lo_src;
         } else {
-            iv.clamp(0.0, sn, sd);
+            src = iv.clamp(0.0, 1.0, sn, sd);
         }
         const double s = sn / sd;
         const double c0 = ci / mm;
         vx = c0 * mx - s * my;
         vy = c0 * my + s * mx;
+        if (REC) {
+            act->line = i;
+            act->src = src;
+        }
     }
     return true;
 }
@@ -285,11 +329,18 @@ ORCA_HD inline bool lp2_plane(const Lane &L, int k, double2 nk, double bk, doubl
 // incremental 3D program in (v, t) with t >= 0, starting from a point that
 // satisfies constraints 0..start-1 (so t = 0 is optimal for them).  When
 // constraint k is violated beyond the current t, the new optimum has
-// t = b_k - n_k . v: maximise n_k . v on that plane.
-ORCA_HD inline double lp3_least_penetration(const Lane &L, int m, int start, double vmax, double &vx,
-                                        double &vy)
+// t = b_k - n_k . v: maximise n_k . v on that plane.  With REC the plane of
+// the last accepted step (-1: none) and its program's Active are recorded.
+template <bool REC>
+ORCA_HD inline double lp3_least_penetration(const Lane &L, int m, int start, double vmax,
+                                            double &vx, double &vy, int *plane, Active *act)
 {
     double t = 0.0;
+    if (REC) {
+        *plane = -1;
+        act->line = kLineNone;
+        act->src = kSrcDisc;
+    }
     for (int k = start; k < m; ++k) {
         const double2 nk = L.N(k);
         const double bk = L.B(k);
@@ -297,10 +348,15 @@ ORCA_HD inline double lp3_least_penetration(const Lane &L, int m, int start, dou
         if (nk.x * vx + nk.y * vy + t >= bk) continue;
         ORCA_COUNT(lp3_plane);
         double wx, wy;
-        if (lp2_plane(L, k, nk, bk, vmax, wx, wy)) {
+        Active pa;
+        if (lp2_plane<REC>(L, k, nk, bk, vmax, wx, wy, &pa)) {
             vx = wx;
             vy = wy;
             t = fmax(bk - (nk.x * vx + nk.y * vy), 0.0);
+            if (REC) {
+                *plane = k;
+                *act = pa;
+            }
         }
     }
     return t;

@@ -207,7 +207,16 @@ class Context:
         return choice[0], choice[1]
 
     def backward(self, tape_step, g_pos_next, g_vel_next, g_pos, g_vel, g_pref_vel,
-                 g_max_speed, g_time_horizon):
+                 g_max_speed=None, g_time_horizon=None):
+        """Adjoint of recorded step tape_step (see orca_backward): writes g_pos, g_vel,
+        adds to g_pref_vel, g_max_speed [n_scenes], g_time_horizon [n_scenes]."""
+        n = g_pos.shape[1]
+        for t, nm in ((g_pos_next, "g_pos_next"), (g_vel_next, "g_vel_next"), (g_pos, "g_pos"),
+                      (g_vel, "g_vel"), (g_pref_vel, "g_pref_vel")):
+            _dev_ptr(t, nm, n)
+        for t, nm in ((g_max_speed, "g_max_speed"), (g_time_horizon, "g_time_horizon")):
+            if t is not None:
+                _dev_ptr(t, nm, shape2=False)
         self._sync_stream()
         ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
         self._check(self.lib.orca_backward(self.h, int(tape_step), ptr(g_pos_next),

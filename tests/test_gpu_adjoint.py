@@ -1,0 +1,126 @@
+"""Adjoint of the GPU step against the reference's forward mode.
+
+  * per step: <gbar, J delta> from the reference's complex-step tangent of one
+    step equals <J^T gbar, delta> from orca_backward, from the same float32
+    state (dot-product test), for position, velocity, preferred velocity,
+    max speed and time horizon;
+  * recording a step does not change it;
+  * a whole trajectory (4,096 agents, 200 steps, checkpoints every 20
+    steps): the gradient of L = sum |x(T) - y|^2 through OrcaTrajectory
+    against the reference's forward-mode derivative of the same float32-state
+    trajectory along random directions and along max speed and time horizon,
+    within 1e-3 relative.  (The forward mode itself is pinned against
+    central finite differences of the float64 reference in
+    test_oracle_grad.py.)
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_10107_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def moving_scene(n, density, seed, **over):
+    """Uniform square with random current velocities and fixed preferred ones."""
+    w = scenes.grad(n=n, density=density, seed=seed, **over)
+    rng = np.random.default_rng(seed + 7)
+    w.vel = np.ascontiguousarray((rng.normal(size=(2, n)) * 0.7).astype(np.float32))
+    return w
+
+
+@pytest.mark.parametrize("case", ["moderate", "dense"])
+def test_step_vjp_dot_product(case):
+    torch = _torch()
+    from paper_1908_10107_amd import orca
+    say("case step vjp", case)
+    w = moving_scene(3000, 1.0, 41) if case == "moderate" else moving_scene(3000, 2.5, 42)
+    d = orca.to_device(w)
+    k = w.params[0].max_neighbors
+    ctx = orca.Context(max_agents=w.n, max_scenes=1, k_max=k, tape_steps=1)
+    p1, v1 = d["pos"].clone(), d["vel"].clone()
+    ctx.step(w.offsets, w.params, p1, v1, d["pref_vel"], n_steps=1, save_tape=True)
+    p2, v2 = d["pos"].clone(), d["vel"].clone()
+    ctx.step(w.offsets, w.params, p2, v2, d["pref_vel"], n_steps=1)
+    torch.cuda.synchronize()
+    assert torch.equal(p1, p2) and torch.equal(v1, v2)
+    rng = np.random.default_rng(3)
+    for trial in range(3):
+        gxn = rng.normal(size=(2, w.n)).astype(np.float32)
+        gvn = rng.normal(size=(2, w.n)).astype(np.float32)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        gx, gv = torch.zeros_like(d["pos"]), torch.zeros_like(d["pos"])
+        gp = torch.zeros_like(d["pos"])
+        gvm = torch.zeros(1, device="cuda")
+        gta = torch.zeros(1, device="cuda")
+        ctx.backward(0, t(gxn), t(gvn), gx, gv, gp, gvm, gta)
+        torch.cuda.synchronize()
+        dpos, dvel, dpref = (rng.normal(size=(2, w.n)) for _ in range(3))
+        dvm, dta = rng.normal(size=1), rng.normal(size=1)
+        if trial == 1:
+            dpos[:] = 0.0
+            dvel[:] = 0.0   # parameters only
+        jp, jv = oracle.step_jvp(w.pos, w.vel, w.pref_vel, w.offsets, w.params, dpos, dvel,
+                                 dpref, dvm, dta)
+        lhs = float((gxn.astype(np.float64) * jp).sum() + (gvn.astype(np.float64) * jv).sum())
+        G = lambda a: a.cpu().numpy().astype(np.float64)
+        rhs = float((G(gx) * dpos).sum() + (G(gv) * dvel).sum() + (G(gp) * dpref).sum()
+                    + G(gvm)[0] * dvm[0] + G(gta)[0] * dta[0])
+        say("  dot test %s trial %d: <g, J d> = %.9g, <J^T g, d> = %.9g" % (case, trial, lhs, rhs))
+        assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + abs(rhs)) + 1e-6, (lhs, rhs)
+    ctx.close()
+
+
+def test_trajectory_gradient_200_steps():
+    torch = _torch()
+    from paper_1908_10107_amd import autograd, orca
+    say("case trajectory gradient 4096 x 200")
+    w = scenes.grad()
+    d = orca.to_device(w)
+    p = w.params[0]
+    pref = d["pref_vel"].clone().requires_grad_(True)
+    vmax = torch.tensor([p.max_speed], device="cuda", requires_grad=True)
+    tau = torch.tensor([p.time_horizon], device="cuda", requires_grad=True)
+    spec = autograd.TrajectorySpec(offsets=list(w.offsets), params=list(w.params),
+                                   n_steps=w.steps, segment=20)
+    pos, vel = autograd.trajectory(d["pos"], d["vel"], pref, vmax, tau, spec)
+    y = torch.from_numpy(w.targets).cuda()
+    loss = ((pos.double() - y.double()) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    g_pref = pref.grad.cpu().numpy().astype(np.float64)
+    g_vmax = float(vmax.grad.cpu()[0])
+    g_tau = float(tau.grad.cpu()[0])
+    say("  loss %.6f  |dL/dvhat| %.4g  dL/dvmax %.6g  dL/dtau %.6g"
+        % (float(loss), np.linalg.norm(g_pref), g_vmax, g_tau))
+    rng = np.random.default_rng(9)
+    pos0 = w.pos.astype(np.float64)
+    vel0 = w.vel.astype(np.float64)
+    pr = w.pref_vel.astype(np.float64)
+    vm, ta = np.array([np.float32(p.max_speed)], float), np.array([np.float32(p.time_horizon)], float)
+    dirs = [("vmax", np.zeros_like(pr), np.ones(1), np.zeros(1)),
+            ("tau", np.zeros_like(pr), np.zeros(1), np.ones(1))]
+    for k in range(3):
+        dirs.append(("rand%d" % k, rng.normal(size=pr.shape), np.zeros(1), np.zeros(1)))
+    for name, dp, dv, dt_ in dirs:
+        L, dL = oracle.traj_jvp(pos0, vel0, pr, w.offsets, w.params, vm, ta, w.steps, w.targets,
+                                dp, dv, dt_, f32_state=True)
+        mine = float((g_pref * dp).sum() + g_vmax * dv[0] + g_tau * dt_[0])
+        say("  direction %-6s: adjoint %.8g  forward mode %.8g  (loss %.6f)" % (name, mine, dL, L))
+        assert abs(mine - dL) <= 1e-3 * max(abs(dL), 1e-6 * abs(L)), (name, mine, dL)
+    spec.ctx.close()
