@@ -29,20 +29,57 @@ METRIC = "agent-steps/s at 1M agents (plain vs batched vs fwd+adjoint, 1e-4 m/s)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
-# Algorithmic bytes per agent of each stage (every array touched once; the
-# neighbours' re-reads are cache traffic, not counted).  K = neighbour cap.
-#   binning:    bbox 8 + key pass 28 + scatter 60          = 96 per agent, + 12 per cell
-#   neighbours: own row 28 + list 4K + count 4              = 32 + 4K
-#   lp2d:       own row 36 + list 4K + goal 8 + outputs 24  = 68 + 4K
-#   fallback:   the same for each fallback agent, + list 4  = 72 + 4K
-def stage_bytes(stage: int, n: int, k: int, cells: int, n_fallback: float) -> float:
+# Algorithmic work of each stage.
+#   binning (HBM): bbox 8 + key pass 28 + scatter 60 = 96 B per agent, + 12 B per cell.
+#   neighbours (HBM figure): own row 28 + list 4K + count 4 = 32 + 4K B per agent.
+#   half-planes + 2D LP (FP64 ALU): 29.2 K + 14.0 K operations per agent
+#     (half-plane construction and projection; 691 at K = 16).
+#   fallback (FP64 ALU): 40.75 K operations per fallback agent (652 at K = 16).
+# The FP64 operation counts were taken from the programs as written (each
+# multiply, add, fused multiply-add, divide or square root counts once) on a
+# dense evolved state; see the roofline section of the design notes.
+HP_OPS_PER_K = 29.2
+LP2_OPS_PER_K = 14.0
+FB_OPS_PER_K = 40.75
+
+
+def stage_roofline(stage: int, ms: float, n: int, k: int, cells: int, n_fallback: float):
+    """(bound, achieved, peak, unit) of one stage at its average duration ms."""
+    s = ms * 1e-3
     if stage == 0:
-        return 96.0 * n + 12.0 * cells
+        return "hbm", (96.0 * n + 12.0 * cells) / s / 1e9, HBM_PEAK_GBS, "GB/s"
     if stage == 1:
-        return (32.0 + 4.0 * k) * n
+        return "hbm", (32.0 + 4.0 * k) * n / s / 1e9, HBM_PEAK_GBS, "GB/s"
     if stage == 2:
-        return (68.0 + 4.0 * k) * n
-    return (72.0 + 4.0 * k) * n_fallback
+        return "alu", (HP_OPS_PER_K + LP2_OPS_PER_K) * k * n / s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
+    return "alu", FB_OPS_PER_K * k * n_fallback / s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
+
+
+PROFILE_MD = os.path.join(ROOT, "profiles", "dense_uniform_1M_kernels.md")
+KERNEL_SOURCES = ("paper_1908_10107_amd/csrc/orca_kernels.hip", "paper_1908_10107_amd/csrc/orca_lp.h",
+                  "paper_1908_10107_amd/csrc/orca_internal.h")
+
+
+def profiled_traffic(kernel: str):
+    """HBM bytes per dispatch of ``kernel`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel), or None when
+    the kernel sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(PROFILE_MD).read()
+    except OSError:
+        return None
+    d = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            d.update(fh.read())
+    if "kernel-source-sha256: %s " % d.hexdigest()[:16] not in text:
+        return None
+    tag = "traffic-bytes-per-dispatch %s: " % kernel
+    for line in text.splitlines():
+        if line.startswith(tag):
+            return float(line[len(tag):])
+    return None
 
 
 def make_workload(name: str):
@@ -58,19 +95,23 @@ def make_workload(name: str):
     raise SystemExit("unknown workload %s" % name)
 
 
-def cpu_baseline(w, sample: int):
-    """The reference's rate on one step of ``sample`` agents of the same state."""
+def cpu_baseline(w, min_seconds: float):
+    """The reference's rate on whole steps of the same workload from its
+    initial state, stepped one at a time until ``min_seconds`` have passed."""
     import oracle
-    rng = np.random.default_rng(0)
-    agents = np.sort(rng.choice(w.n, size=min(sample, w.n), replace=False))
+    pos, vel, pref = w.pos, w.vel, w.pref_vel
+    steps = 0
     t0 = time.perf_counter()
-    oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params, goals=w.goals,
-                      agents=agents, neighbor_mode=1)
-    dt = time.perf_counter() - t0
-    return dict(value=len(agents) / dt, unit="agent-steps/s", cores=oracle.threads(),
+    while True:
+        pos, vel, pref, _ = oracle.step(pos, vel, pref, w.offsets, w.params, goals=w.goals)
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds or steps >= 200:
+            break
+    return dict(value=w.n * steps / dt, unit="agent-steps/s", cores=oracle.threads(),
                 kind="oracle",
-                sample="one step of %d of the %d agents from the initial state (binning of all "
-                       "agents included), %.1f s" % (len(agents), w.n, dt))
+                sample="%d whole steps of all %d agents from the initial state, %.1f s"
+                       % (steps, w.n, dt))
 
 
 def batched_forms(steps: int, no_autotune: bool):
@@ -122,6 +163,49 @@ def batched_forms(steps: int, no_autotune: bool):
             "batched_speedup": bg / bp}
 
 
+def adjoint_forms():
+    """Forward + adjoint: the 4,096-agent 200-step trajectory with checkpoints
+    every 20 steps, and one 20-step segment at 1,048,576 agents.  A step of
+    the forward counts once; the time includes the checkpointed forward, the
+    recorded replay and the adjoint steps."""
+    import torch
+    from paper_1908_10107_amd import autograd, orca, scenes
+    out = {}
+    for name, w, steps in (("grad_4096x200", scenes.grad(), 200),
+                           ("dense_1M_segment20", scenes.dense_uniform(), 20)):
+        if name.startswith("dense"):
+            w.goals = None  # fixed preferred velocities for the differentiable form
+            rng = np.random.default_rng(4)
+            a = rng.uniform(0, 2 * np.pi, w.n)
+            w.pref_vel = np.ascontiguousarray((1.3 * np.stack([np.cos(a), np.sin(a)]))
+                                              .astype(np.float32))
+        d = orca.to_device(w)
+        p = w.params[0]
+        spec = autograd.TrajectorySpec(offsets=list(w.offsets), params=list(w.params),
+                                       n_steps=steps, segment=20)
+
+        def run():
+            pref = d["pref_vel"].clone().requires_grad_(True)
+            vmax = torch.tensor([p.max_speed], device="cuda", requires_grad=True)
+            tau = torch.tensor([p.time_horizon], device="cuda", requires_grad=True)
+            pos, vel = autograd.trajectory(d["pos"], d["vel"], pref, vmax, tau, spec)
+            (pos.double() ** 2).sum().backward()
+            return pref.grad
+
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3 if w.n < 100000 else 1
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"value": w.n * steps / dt, "unit": "agent-steps/s", "agents": w.n,
+                     "steps": steps, "ms_per_step": 1e3 * dt / steps, "segment": 20}
+        spec.ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,13 +213,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="dense_uniform")
     ap.add_argument("--profile-steps", type=int, default=10)
-    ap.add_argument("--cpu-sample", type=int, default=262144)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="the CPU reference steps the workload until this much time has passed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,batched",
+    ap.add_argument("--forms", default="plain,batched,adjoint",
                     help="comma list: plain (always), batched (512 scenes, graph replay vs "
-                         "per-scene plain steps)")
+                         "per-scene plain steps), adjoint (forward + adjoint)")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--launch", default=None,
+                    help="KNN_BLOCK,FALLBACK_WAVES_PER_CU: fixed launch shapes instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise copy of 256 MiB (reads and writes known bytes) "
                          "to scale hardware byte counters")
@@ -158,7 +245,10 @@ def main():
     step = lambda k: ctx.step(w.offsets, w.params, st["pos"], st["vel"], st["pref"],
                               goals=base["goals"], n_steps=k)
     tuned = None
-    if not args.no_autotune:
+    if args.launch:
+        tuned = tuple(int(x) for x in args.launch.split(","))
+        ctx.set_launch(*tuned)
+    elif not args.no_autotune:
         ctx.build_grid(w.offsets, w.params, st["pos"])
         tuned = ctx.autotune(st["pos"], st["vel"], st["pref"], goals=base["goals"], reps=2)
     if args.warmup:
@@ -187,14 +277,22 @@ def main():
     fb_avg = fb / max(passes, 1)
     dom = int(np.argmax(avg))
     cells = 4 * w.n  # upper bound of the cell budget; the 12 B/cell term is small
-    alg = stage_bytes(dom, w.n, kmax, cells, fb_avg)
-    achieved = alg / (avg[dom] * 1e-3) / 1e9
     stages = {orca.STAGE_NAMES[i]: round(avg[i], 4) for i in range(orca.PROF_STAGES)}
-    roofline = dict(bound="hbm", achieved=round(achieved, 3), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 6), traffic=None,
-                    kernel="k_fallback" if dom == 3 else ("k_lp" if dom == 2 else
-                                                          ("k_knn" if dom == 1 else "binning")),
-                    stage_ms=stages, fallback_agents_per_step=round(fb_avg, 1))
+    bound, achieved, peak, unit = stage_roofline(dom, avg[dom], w.n, kmax, cells, fb_avg)
+    others = {}
+    for i in range(orca.PROF_STAGES):
+        b_, a_, p_, u_ = stage_roofline(i, avg[i], w.n, kmax, cells, fb_avg)
+        others[orca.STAGE_NAMES[i]] = {"bound": b_, "achieved": round(a_, 4), "unit": u_,
+                                       "frac": round(a_ / p_, 6)}
+    kdisp = 10 if kmax <= 10 else (16 if kmax <= 16 else 32)
+    kname = ("k_key", "k_knn<%d>" % kdisp, "k_lp<%d,false>" % kdisp,
+             "k_fallback<%d,false>" % kdisp)[dom]
+    traffic = profiled_traffic(kname) if args.workload == "dense_uniform" else None
+    roofline = dict(bound=bound, achieved=round(achieved, 4), peak=peak, unit=unit,
+                    frac=round(achieved / peak, 6), traffic=traffic, traffic_unit="B/launch",
+                    kernel=kname,
+                    stage_ms=stages, stages=others,
+                    fallback_agents_per_step=round(fb_avg, 1))
 
     # the same plain step replayed from a captured graph (launch cost only differs)
     gstep = lambda k: ctx.step_graph(w.offsets, w.params, st["pos"], st["vel"], st["pref"],
@@ -211,6 +309,8 @@ def main():
     del st, base
     if "batched" in args.forms.split(","):
         forms.update(batched_forms(args.batched_steps, args.no_autotune))
+    if "adjoint" in args.forms.split(","):
+        forms.update(adjoint_forms())
 
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -220,7 +320,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_sample)
+        cpu = cpu_baseline(w, args.cpu_seconds)
 
     line = {
         "metric": METRIC, "value": value, "unit": "agent-steps/s", "n_gpus": 1,

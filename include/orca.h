@@ -179,6 +179,14 @@ int orca_autotune(orca_ctx *ctx, const float *pos, const float *vel, const float
                   const float *goals, float *new_vel, int32_t reps, int32_t *choice);
 
 /*
+ * Set the launch shapes directly (the two values orca_autotune picks):
+ * knn_block in {64, 128, 256, 512} threads per neighbour block and
+ * fb_waves_per_cu in 1..64 persistent fallback waves per compute unit.
+ * Results do not depend on them.  Errors: EINVAL.
+ */
+int orca_set_launch(orca_ctx *ctx, int32_t knn_block, int32_t fb_waves_per_cu);
+
+/*
  * Vector-Jacobian product of recorded step tape_step (0-based, of the last
  * orca_step call with save_tape = 1; no goals).  Given the gradients of a loss
  * with respect to the state after the step (g_pos_next, g_vel_next, device

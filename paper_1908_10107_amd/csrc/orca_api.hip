@@ -587,6 +587,18 @@ int orca_autotune(orca_ctx *ctx, const float *pos, const float *vel, const float
     return ORCA_OK;
 }
 
+int orca_set_launch(orca_ctx *ctx, int32_t knn_block, int32_t fb_waves_per_cu)
+{
+    if (!ctx) return ORCA_EINVAL;
+    if (knn_block != 64 && knn_block != 128 && knn_block != 256 && knn_block != 512)
+        return fail(ctx, ORCA_EINVAL, "knn_block must be 64, 128, 256 or 512");
+    if (fb_waves_per_cu < 1 || fb_waves_per_cu > 64)
+        return fail(ctx, ORCA_EINVAL, "fb_waves_per_cu must be in 1..64");
+    ctx->knn_block = knn_block;
+    ctx->fb_waves_per_cu = fb_waves_per_cu;
+    return ORCA_OK;
+}
+
 int orca_profile(orca_ctx *ctx, int32_t enable)
 {
     if (!ctx) return ORCA_EINVAL;

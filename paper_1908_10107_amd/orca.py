@@ -80,6 +80,8 @@ def load(path: str = LIB_PATH):
     L.orca_step_graph.restype = ctypes.c_int
     L.orca_autotune.argtypes = [_P, _P, _P, _P, _P, _P, ctypes.c_int32, _P]
     L.orca_autotune.restype = ctypes.c_int
+    L.orca_set_launch.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
+    L.orca_set_launch.restype = ctypes.c_int
     L.orca_profile.argtypes = [_P, ctypes.c_int32]
     L.orca_profile.restype = ctypes.c_int
     L.orca_profile_read.argtypes = [_P, _P, _P, _P]
@@ -205,6 +207,10 @@ class Context:
                                            _dev_ptr(goals, "goals", n), _dev_ptr(scratch, "new_vel", n),
                                            int(reps), choice))
         return choice[0], choice[1]
+
+    def set_launch(self, knn_block, fallback_waves_per_cu):
+        """Fix the launch shapes that autotune would pick (see orca_set_launch)."""
+        self._check(self.lib.orca_set_launch(self.h, int(knn_block), int(fallback_waves_per_cu)))
 
     def backward(self, tape_step, g_pos_next, g_vel_next, g_pos, g_vel, g_pref_vel,
                  g_max_speed=None, g_time_horizon=None):

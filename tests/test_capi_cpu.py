@@ -51,6 +51,7 @@ def test_null_context_calls(lib):
     assert lib.orca_step(None, 1, None, None, None, None, None, None, 1, 0) == orca.EINVAL
     assert lib.orca_backward(None, 0, *([None] * 7)) == orca.EINVAL
     assert lib.orca_set_stream(None, None) == orca.EINVAL
+    assert lib.orca_set_launch(None, 256, 16) == orca.EINVAL
     lib.orca_destroy(None)
 
 
