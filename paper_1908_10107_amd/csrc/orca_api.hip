@@ -42,6 +42,8 @@ struct orca_ctx {
     int32_t *sid = nullptr, *skey = nullptr, *inv = nullptr;
     int32_t *nbr = nullptr, *ncount = nullptr;
     orca::FallbackItem *fb_list = nullptr;
+    uint8_t *fb_key = nullptr;
+    int32_t *fb_order = nullptr;
     double2 *stash_n = nullptr;
     double *stash_b = nullptr;
     std::vector<void *> allocs;
@@ -236,7 +238,10 @@ orca::Plan make_plan(const orca_ctx *ctx)
     p.inv = ctx->inv;
     p.nbr = ctx->nbr;
     p.ncount = ctx->ncount;
+    p.kcap = ctx->k_max;
     p.fb_list = ctx->fb_list;
+    p.fb_key = ctx->fb_key;
+    p.fb_order = ctx->fb_order;
     p.stash_n = ctx->stash_n;
     p.stash_b = ctx->stash_b;
     return p;
@@ -367,6 +372,8 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->nbr, sizeof(int32_t) * A * (size_t)k_max) &&
               alloc((void **)&ctx->ncount, sizeof(int32_t) * A) &&
               alloc((void **)&ctx->fb_list, sizeof(orca::FallbackItem) * A) &&
+              alloc((void **)&ctx->fb_key, sizeof(uint8_t) * A) &&
+              alloc((void **)&ctx->fb_order, sizeof(int32_t) * A) &&
               alloc((void **)&ctx->stash_n, sizeof(double2) * A * (size_t)k_max) &&
               alloc((void **)&ctx->stash_b, sizeof(double) * A * (size_t)k_max) &&
               alloc((void **)&ctx->acc, sizeof(double) * 4 * A) &&

@@ -14,6 +14,8 @@ constexpr int kScanTile = kScanItems * kScanBlock;  // cells per scan tile
 constexpr int kLpBlock = 64;                        // one wave per LP block
 constexpr int kBboxChunk = 8192;                    // agents per bounding-box block
 constexpr double kCellMargin = 1.0 + 1.0 / 1024.0;  // cell side / neighbor_dist
+constexpr int kFbSortChunk = 4096;                  // fallback slots sorted together
+constexpr int kFbSortBlock = 256;
 
 // Per-scene parameters as the kernels read them.
 struct SceneDev {
@@ -36,13 +38,17 @@ struct Counters {
 
 // An agent whose projection was empty, with what the fallback needs to
 // finish it without touching the agent arrays again: sorted index, id, number
-// of half-planes, the row at which the projection failed, the optimum of the
-// rows before it, the preferred velocity, max speed, dt and position.
+// of half-planes, the row at which the projection failed, the line and bound
+// that fix the optimum of the rows before it (an Active, as int8), that
+// optimum, the preferred velocity, max speed, dt and position.
 struct FallbackItem {
-    int32_t s, id, m, fail;
+    int32_t s, id;
+    int8_t m, fail, line, src;
+    int32_t pad;
     double vx, vy, vhx, vhy;
     float vmax, dt, mex, mey;
 };
+static_assert(sizeof(FallbackItem) == 64, "one fallback record per 64-byte line");
 
 // Where the velocity kernels put their results.  Step mode has pos != nullptr.
 struct OutArgs {
@@ -76,9 +82,12 @@ struct Plan {
     float4 *sorted;
     int32_t *sid, *skey, *inv;
     int32_t *nbr, *ncount;
+    int32_t kcap;      // rows per stash slot (the context's k_max)
     FallbackItem *fb_list;
-    double2 *stash_n;  // [k_max, ld] half-plane normals of fallback slots
-    double *stash_b;   // [k_max, ld] half-plane offsets
+    uint8_t *fb_key;   // [ld] failed row of each fallback slot (the sort key)
+    int32_t *fb_order; // [ld] fallback slots, sorted by fb_key within chunks of kFbSortChunk
+    double2 *stash_n;  // [ld, kcap] half-plane normals of fallback slots, one slot contiguous
+    double *stash_b;   // [ld, kcap] half-plane offsets
     OutArgs out;
 };
 

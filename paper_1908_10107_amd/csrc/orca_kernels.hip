@@ -530,8 +530,8 @@ __device__ __forceinline__ void write_result(const OutArgs &o, float mex, float 
 
 // One lane per agent in cell order.  Feasible agents finish here; an agent
 // whose projection is empty is handed to the fallback list with everything
-// k_fallback needs (one atomic per wave), and its half-planes go to column
-// `slot` of the stash.
+// k_fallback needs (one atomic per wave): its record, its sort key (the failed
+// row) and its half-planes in stash slot `slot`.
 template <int KMAX, bool REC>
 __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sorted,
                                                  const int32_t *__restrict__ sid,
@@ -540,6 +540,7 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
                                                  const int32_t *__restrict__ nbr, int32_t ld,
                                                  const int32_t *__restrict__ ncount,
                                                  OutArgs out, FallbackItem *__restrict__ fb_list,
+                                                 uint8_t *__restrict__ fb_key, int32_t kcap,
                                                  double2 *__restrict__ stash_n,
                                                  double *__restrict__ stash_b,
                                                  Counters *__restrict__ counters)
@@ -562,7 +563,7 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
         const int m = build_constraints(L, s, id, me, p, sorted, sid, nbr, ld, ncount,
                                         out.nbr_out, out.krow);
         Active act;
-        const int fail = lp2_project<REC>(L, m, 0, 0.0, vmax, vhx, vhy, vx, vy, &act);
+        const int fail = lp2_project<true>(L, m, 0, 0.0, vmax, vhx, vhy, vx, vy, &act);
         if (REC) out.tape_state[id] = me;
         if (fail < 0) {
             write_result(out, me.x, me.y, p.dt, id, n, vx, vy, vhx, vhy, 0);
@@ -580,8 +581,10 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
             need_fb = true;
             it.s = s;
             it.id = id;
-            it.m = m;
-            it.fail = fail;
+            it.m = (int8_t)m;
+            it.fail = (int8_t)fail;
+            it.line = (int8_t)act.line;
+            it.src = (int8_t)act.src;
             it.vx = vx;
             it.vy = vy;
             it.vhx = vhx;
@@ -604,44 +607,171 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
         if (need_fb) {
             const uint32_t slot = slot0 + before;
             fb_list[slot] = it;
+            fb_key[slot] = (uint8_t)it.fail;
+            double2 *gn = stash_n + (int64_t)slot * kcap;
+            double *gb = stash_b + (int64_t)slot * kcap;
             for (int k = 0; k < it.m; ++k) {
-                stash_n[(int64_t)k * ld + slot] = L.N(k);
-                stash_b[(int64_t)k * ld + slot] = L.B(k);
+                gn[k] = L.N(k);
+                gb[k] = L.B(k);
             }
         }
     }
 }
 
-// Persistent over the fallback list: load the half-planes k_lp stashed, find
-// the least penetration d* from the projection's last optimum (the rows
-// before the failed one are satisfied there with t = 0), then take the point
-// closest to vhat among those within d* + delta of every half-plane.
+// Counting sort of each chunk of kFbSortChunk fallback slots by the row at
+// which their projection failed, so that a wave of k_fallback takes agents
+// whose programs start at the same row and follow similar paths.  Order
+// within a key is whatever the LDS atomics give; results do not depend on it.
+__global__ __launch_bounds__(kFbSortBlock) void k_fb_sort(const uint8_t *__restrict__ key,
+                                                          int32_t *__restrict__ order,
+                                                          const Counters *__restrict__ counters)
+{
+    constexpr int kPer = kFbSortChunk / kFbSortBlock;
+    __shared__ uint32_t hist[64];
+    const uint32_t count = counters->n_fallback;
+    const uint32_t c0 = blockIdx.x * (uint32_t)kFbSortChunk;
+    if (c0 >= count) return;  // uniform over the block
+    const uint32_t c1 = min(c0 + (uint32_t)kFbSortChunk, count);
+    if (threadIdx.x < 64) hist[threadIdx.x] = 0u;
+    __syncthreads();
+    uint32_t rk[kPer];
+    uint32_t kv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const uint32_t i = c0 + q * kFbSortBlock + threadIdx.x;
+        kv[q] = 0u;
+        rk[q] = 0u;
+        if (i < c1) {
+            kv[q] = key[i] & 63u;
+            rk[q] = atomicAdd(&hist[kv[q]], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const uint32_t v = hist[threadIdx.x];
+        uint32_t inc = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o, 64);
+            if ((int)threadIdx.x >= o) inc += u;
+        }
+        hist[threadIdx.x] = inc - v;  // exclusive
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const uint32_t i = c0 + q * kFbSortBlock + threadIdx.x;
+        if (i < c1) order[c0 + hist[kv[q]] + rk[q]] = (int32_t)i;
+    }
+}
+
+// Exchange rows a and b of a lane's constraint column (and, when recording,
+// of its column of original row indices).
+template <bool REC>
+__device__ __forceinline__ void swap_rows(const Lane &L, int8_t *idx, int a, int b)
+{
+    if (a == b) return;
+    const double2 na = L.N(a), nb = L.N(b);
+    const double ba = L.B(a), bb = L.B(b);
+    L.n[a * kLpStride] = nb;
+    L.n[b * kLpStride] = na;
+    L.b[a * kLpStride] = bb;
+    L.b[b * kLpStride] = ba;
+    if (REC) {
+        const int8_t t = idx[a * kLpStride];
+        idx[a * kLpStride] = idx[b * kLpStride];
+        idx[b * kLpStride] = t;
+    }
+}
+
+// Move up to three distinct rows (negative entries are not rows) to the front,
+// in the order given.
+template <bool REC>
+__device__ __forceinline__ void rows_to_front(const Lane &L, int8_t *idx, int r0, int r1, int r2)
+{
+    int p = 0;
+    if (r0 >= 0) {
+        swap_rows<REC>(L, idx, p, r0);
+        if (r1 == p) r1 = r0;
+        if (r2 == p) r2 = r0;
+        ++p;
+    }
+    if (r1 >= 0) {
+        swap_rows<REC>(L, idx, p, r1);
+        if (r2 == p) r2 = r1;
+        ++p;
+    }
+    if (r2 >= 0) swap_rows<REC>(L, idx, p, r2);
+}
+
+// Original row of a recorded row position (negative codes pass through).
+__device__ __forceinline__ int8_t orig_row(const int8_t *idx, int r)
+{
+    return r >= 0 ? idx[r * kLpStride] : (int8_t)r;
+}
+
+// Persistent over the fallback list in sorted order.  The programs' results
+// do not depend on the order of their rows, only their cost does, so rows are
+// moved first:
+//   * the rows that fix the projection's last optimum to the front of the
+//     rows before the failed one, and the most violated of the rest to the
+//     failed position: the least-penetration program then meets few
+//     violations after its first plane;
+//   * after it, the rows that fix d* to the front: the relaxed projection's
+//     optimum lies where they cross, so later rows are rarely violated.
+// Then d* from the projection's last optimum (the rows before the failed one
+// hold there with t = 0), and the point closest to vhat among those within
+// d* + delta of every half-plane.
 template <int KMAX, bool REC>
-__global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, int32_t ld,
+__global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, int32_t kcap,
                                                        const FallbackItem *__restrict__ fb_list,
+                                                       const int32_t *__restrict__ fb_order,
                                                        const double2 *__restrict__ stash_n,
                                                        const double *__restrict__ stash_b,
                                                        const Counters *__restrict__ counters)
 {
     __shared__ double2 s_n[KMAX * kLpBlock];
     __shared__ double s_b[KMAX * kLpBlock];
+    __shared__ int8_t s_idx[REC ? KMAX * kLpBlock : 1];
     const uint32_t count = counters->n_fallback;
     const Lane L{s_n + threadIdx.x, s_b + threadIdx.x};
-    for (uint32_t idx = blockIdx.x * kLpBlock + threadIdx.x; idx < count;
-         idx += gridDim.x * kLpBlock) {
-        const FallbackItem it = fb_list[idx];
-        const int m = it.m;
-        for (int k = 0; k < m; ++k) {
-            L.n[k * kLpBlock] = stash_n[(int64_t)k * ld + idx];
-            L.b[k * kLpBlock] = stash_b[(int64_t)k * ld + idx];
-        }
-        const double vmax = (double)it.vmax;
+    int8_t *idx_col = REC ? s_idx + threadIdx.x : s_idx;
+    for (uint32_t q = blockIdx.x * kLpBlock + threadIdx.x; q < count; q += gridDim.x * kLpBlock) {
+        const int32_t slot = fb_order[q];
+        const FallbackItem it = fb_list[slot];
+        const int m = it.m, fail = it.fail;
+        const double2 *gn = stash_n + (int64_t)slot * kcap;
+        const double *gb = stash_b + (int64_t)slot * kcap;
         double vx = it.vx, vy = it.vy;
+        int worst = fail;
+        double wv = -1.0e300;
+        for (int k = 0; k < m; ++k) {
+            const double2 nk = gn[k];
+            const double bk = gb[k];
+            L.n[k * kLpStride] = nk;
+            L.b[k * kLpStride] = bk;
+            if (REC) idx_col[k * kLpStride] = (int8_t)k;
+            const double viol = bk - (nk.x * vx + nk.y * vy);
+            if (k >= fail && viol > wv) {
+                wv = viol;
+                worst = k;
+            }
+        }
+        swap_rows<REC>(L, idx_col, fail, worst);
+        rows_to_front<REC>(L, idx_col, it.line, it.src, -1);
+        const double vmax = (double)it.vmax;
         int plane = -1;
-        Active dact, ract;
-        const double d = lp3_least_penetration<REC>(L, m, it.fail, vmax, vx, vy, &plane, &dact);
+        Active dact;
+        const double d = lp3_least_penetration<true>(L, m, fail, vmax, vx, vy, &plane, &dact);
+        int8_t d_plane = 0, d_line = 0, d_src = 0;
+        if (REC) {
+            d_plane = orig_row(idx_col, plane);
+            d_line = orig_row(idx_col, dact.line);
+            d_src = orig_row(idx_col, dact.src);
+        }
+        rows_to_front<REC>(L, idx_col, plane, dact.line, dact.src);
         double wx, wy;
         disc_clip(vmax, it.vhx, it.vhy, wx, wy);
+        Active ract;
         const bool ok =
             lp2_project<REC>(L, m, 0, d + kRelax, vmax, it.vhx, it.vhy, wx, wy, &ract) < 0;
         if (ok) {
@@ -651,11 +781,11 @@ __global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, i
         if (REC) {
             TapeCode tc{};
             tc.status = 1;
-            tc.p_line = (int8_t)ract.line;
-            tc.p_src = (int8_t)ract.src;
-            tc.d_plane = (int8_t)plane;
-            tc.d_line = (int8_t)dact.line;
-            tc.d_src = (int8_t)dact.src;
+            tc.p_line = orig_row(idx_col, ract.line);
+            tc.p_src = orig_row(idx_col, ract.src);
+            tc.d_plane = d_plane;
+            tc.d_line = d_line;
+            tc.d_src = d_src;
             tc.relaxed_empty = ok ? 0 : 1;
             tc.dstar = d;
             out.tape_codes[it.id] = tc;
@@ -684,7 +814,7 @@ hipError_t launch_lp_rec(const Plan &pl, hipStream_t st)
     const int32_t gl = (n + kLpBlock - 1) / kLpBlock;
     hipLaunchKernelGGL((k_lp<KMAX, REC>), dim3(gl), dim3(kLpBlock), 0, st, pl.sorted, pl.sid,
                        pl.agent_scene, pl.sp, n, pl.nbr, pl.ld, pl.ncount, pl.out, pl.fb_list,
-                       pl.stash_n, pl.stash_b, pl.counters);
+                       pl.fb_key, pl.kcap, pl.stash_n, pl.stash_b, pl.counters);
     return hipGetLastError();
 }
 
@@ -692,9 +822,12 @@ template <int KMAX, bool REC>
 hipError_t launch_fallback_rec(const Plan &pl, hipStream_t st)
 {
     // persistent: fb_waves_per_cu one-wave blocks per CU loop over the device-side list
+    const int32_t gs = (pl.n + kFbSortChunk - 1) / kFbSortChunk;
+    hipLaunchKernelGGL(k_fb_sort, dim3(gs), dim3(kFbSortBlock), 0, st, pl.fb_key, pl.fb_order,
+                       pl.counters);
     const int32_t gf = max(1, min((pl.n + kLpBlock - 1) / kLpBlock, pl.fb_waves_per_cu * pl.cus));
-    hipLaunchKernelGGL((k_fallback<KMAX, REC>), dim3(gf), dim3(kLpBlock), 0, st, pl.out, pl.n, pl.ld,
-                       pl.fb_list, pl.stash_n, pl.stash_b, pl.counters);
+    hipLaunchKernelGGL((k_fallback<KMAX, REC>), dim3(gf), dim3(kLpBlock), 0, st, pl.out, pl.n,
+                       pl.kcap, pl.fb_list, pl.fb_order, pl.stash_n, pl.stash_b, pl.counters);
     return hipGetLastError();
 }
 
