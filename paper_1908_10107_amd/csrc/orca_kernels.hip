@@ -367,7 +367,8 @@ __global__ __launch_bounds__(256) void k_fill_vel(const float *__restrict__ vel,
 // K nearest of each agent (sorted order s) among the agents of its 3x3 cells,
 // strictly inside neighbor_dist, nearest first, ties by agent id.  The running
 // list holds (float32 bits of d2) << 32 | id, so one 64-bit compare orders by
-// (d2, id).  Writes nbr[k * ld + s] = the neighbour's sorted index and ncount[s].
+// (d2, id).  Writes nbr[k * ld + s] = the neighbour's sorted index, with bit
+// 31 set when the neighbour's id is the smaller of the pair, and ncount[s].
 template <int KMAX>
 __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
                                              const int32_t *__restrict__ sid,
@@ -386,7 +387,8 @@ __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
     if (s == 0) counters->n_fallback = 0;
     if (s >= n) return;
     const float4 me = sorted[s];
-    const int32_t sc = agent_scene[sid[s]];
+    const int32_t myid = sid[s];
+    const int32_t sc = agent_scene[myid];
     const GridDev g = grid[sc];
     const int32_t K = sp[sc].k;
     const float nd2 = sp[sc].nd2;
@@ -435,7 +437,10 @@ __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         if (k < K && best[k] != ~0ull) {
-            nbr[(int64_t)k * ld + s] = inv[(uint32_t)(best[k] & 0xffffffffu)];
+            const uint32_t jid = (uint32_t)(best[k] & 0xffffffffu);
+            // bit 31: this agent does not come first of the pair (ids order it)
+            const uint32_t later = (uint32_t)myid < jid ? 0u : 0x80000000u;
+            nbr[(int64_t)k * ld + s] = (int32_t)((uint32_t)inv[jid] | later);
             cnt = k + 1;
         }
     }
@@ -451,6 +456,10 @@ namespace orca {
 static_assert(kLpStride == kLpBlock, "LP constraint stride must equal the LP block size");
 
 // Load agent s's neighbours, build the half-planes into the lane's LDS column.
+// All of the neighbour loads are issued before the first half-plane is built,
+// so one memory latency covers them.  Neighbour ids are fetched only when they
+// are written out (the pair order comes with the neighbour entry).
+template <int KMAX>
 __device__ __forceinline__ int build_constraints(const Lane &L, int32_t s, int32_t id, float4 me,
                                                  const SceneDev &p, const float4 *__restrict__ sorted,
                                                  const int32_t *__restrict__ sid,
@@ -462,21 +471,30 @@ __device__ __forceinline__ int build_constraints(const Lane &L, int32_t s, int32
     const double R = 2.0 * (double)p.radius;
     const double tau = (double)p.tau, dt = (double)p.dt;
     const double vix = (double)me.z, viy = (double)me.w;
-    for (int k = 0; k < m; ++k) {
-        const int32_t j = nbr[(int64_t)k * ld + s];
-        const float4 o = sorted[j];
-        const int32_t jid = sid[j];
-        const double Px = (double)o.x - (double)me.x, Py = (double)o.y - (double)me.y;
-        const double Vx = vix - (double)o.z, Vy = viy - (double)o.w;
-        double ux, uy, nx, ny;
-        obstacle_exit(Px, Py, Vx, Vy, R, tau, dt, id < jid, ux, uy, nx, ny);
-        const double qx = vix + 0.5 * ux, qy = viy + 0.5 * uy;
-        L.n[k * kLpBlock] = make_double2(nx, ny);
-        L.b[k * kLpBlock] = nx * qx + ny * qy;
-        if (nbr_out) nbr_out[(int64_t)id * krow + k] = jid;
+    int32_t e[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) e[k] = k < m ? nbr[(int64_t)k * ld + s] : 0;
+    float4 o[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+        o[k] = k < m ? sorted[e[k] & 0x7fffffff] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        if (k < m) {
+            const double Px = (double)o[k].x - (double)me.x, Py = (double)o[k].y - (double)me.y;
+            const double Vx = vix - (double)o[k].z, Vy = viy - (double)o[k].w;
+            double ux, uy, nx, ny;
+            obstacle_exit(Px, Py, Vx, Vy, R, tau, dt, e[k] >= 0, ux, uy, nx, ny);
+            const double qx = vix + 0.5 * ux, qy = viy + 0.5 * uy;
+            L.n[k * kLpBlock] = make_double2(nx, ny);
+            L.b[k * kLpBlock] = nx * qx + ny * qy;
+        }
     }
-    if (nbr_out)
-        for (int k = m; k < krow; ++k) nbr_out[(int64_t)id * krow + k] = -1;
+    if (nbr_out) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < krow) nbr_out[(int64_t)id * krow + k] = k < m ? sid[e[k] & 0x7fffffff] : -1;
+    }
     return m;
 }
 
@@ -560,8 +578,8 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
         const double vmax = (double)p.vmax;
         double vx, vy;
         disc_clip(vmax, vhx, vhy, vx, vy);
-        const int m = build_constraints(L, s, id, me, p, sorted, sid, nbr, ld, ncount,
-                                        out.nbr_out, out.krow);
+        const int m = build_constraints<KMAX>(L, s, id, me, p, sorted, sid, nbr, ld, ncount,
+                                              out.nbr_out, out.krow);
         Active act;
         const int fail = lp2_project<true>(L, m, 0, 0.0, vmax, vhx, vhy, vx, vy, &act);
         if (REC) out.tape_state[id] = me;

@@ -96,4 +96,13 @@ def test_autotune_keeps_results():
     after = ctx.compute_velocities(d["pos"], d["vel"], goals=d["goals"])
     torch.cuda.synchronize()
     assert torch.equal(before, after)
+    for kb, fw in ((64, 1), (128, 8), (256, 64), (512, 32)):
+        ctx.set_launch(kb, fw)
+        again = ctx.compute_velocities(d["pos"], d["vel"], goals=d["goals"])
+        torch.cuda.synchronize()
+        assert torch.equal(before, again), (kb, fw)
+    with pytest.raises(RuntimeError):
+        ctx.set_launch(96, 8)
+    with pytest.raises(RuntimeError):
+        ctx.set_launch(256, 0)
     ctx.close()

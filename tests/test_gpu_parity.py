@@ -126,6 +126,28 @@ def test_coincident_and_head_on():
     compare(w, g, o, label="coincident")
 
 
+@pytest.mark.parametrize("k", [10, 16, 32])
+def test_knn_exact_ties_and_stacked_agents(k):
+    """A 0.5 m lattice (many exactly equal float32 distances, ties at the K-th
+    place broken by id) with 60 agents stacked on one lattice point: more
+    candidates fall below the K-th distance cut-off than the per-lane list
+    holds, so the direct-insertion path runs too."""
+    say("case lattice ties + stack, k=%d" % k)
+    gx, gy = np.meshgrid(np.arange(24) * 0.5, np.arange(24) * 0.5)
+    lat = np.stack([gx.ravel(), gy.ravel()])
+    stack = np.full((2, 60), 6.0)
+    pos = np.ascontiguousarray(np.concatenate([lat, stack], axis=1).astype(np.float32))
+    n = pos.shape[1]
+    rng = np.random.default_rng(k)
+    w = scenes.tiny_random(n, 1.0, seed=k, max_neighbors=k)
+    w.pos = pos
+    w.vel = np.ascontiguousarray((rng.normal(size=(2, n)) * 0.3).astype(np.float32))
+    w.pref_vel = np.ascontiguousarray((rng.normal(size=(2, n)) * 0.8).astype(np.float32))
+    g = gpu_velocities(w, use_goals=False)
+    o = oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params, neighbor_mode=0)
+    compare(w, g, o, label="lattice+stack k=%d" % k)
+
+
 def test_multi_scene_with_empty_scenes():
     say("case multi-scene")
     b = scenes.batched(n_scenes=24, n_min=8, n_max=600, seed=7)
