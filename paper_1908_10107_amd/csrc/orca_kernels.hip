@@ -455,45 +455,92 @@ namespace orca {
 
 static_assert(kLpStride == kLpBlock, "LP constraint stride must equal the LP block size");
 
-// Load agent s's neighbours, build the half-planes into the lane's LDS column.
-// All of the neighbour loads are issued before the first half-plane is built,
-// so one memory latency covers them.  Neighbour ids are fetched only when they
-// are written out (the pair order comes with the neighbour entry).
+// Rows of k_lp: up to 16 in registers (static indices only), more in a
+// per-lane LDS column.
+constexpr int kLpRegRows = 16;
+template <int KMAX, bool IN_REGS = (KMAX <= kLpRegRows)>
+struct LpRows;
 template <int KMAX>
-__device__ __forceinline__ int build_constraints(const Lane &L, int32_t s, int32_t id, float4 me,
+struct LpRows<KMAX, true> {
+    double2 n[KMAX];
+    double b[KMAX];
+    __device__ __forceinline__ void set(int k, double2 nk, double bk)
+    {
+        n[k] = nk;
+        b[k] = bk;
+    }
+    __device__ __forceinline__ double2 N(int k) const { return n[k]; }
+    __device__ __forceinline__ double B(int k) const { return b[k]; }
+    __device__ __forceinline__ int project(int m, double vmax, double vhx, double vhy, double &vx,
+                                          double &vy, Active *act) const
+    {
+        return lp2_project_regs<KMAX>(n, b, m, vmax, vhx, vhy, vx, vy, act);
+    }
+};
+template <int KMAX>
+struct LpRows<KMAX, false> {
+    Lane L;
+    __device__ __forceinline__ void set(int k, double2 nk, double bk)
+    {
+        L.n[k * kLpStride] = nk;
+        L.b[k * kLpStride] = bk;
+    }
+    __device__ __forceinline__ double2 N(int k) const { return L.N(k); }
+    __device__ __forceinline__ double B(int k) const { return L.B(k); }
+    __device__ __forceinline__ int project(int m, double vmax, double vhx, double vhy, double &vx,
+                                          double &vy, Active *act) const
+    {
+        return lp2_project<true>(L, m, 0, 0.0, vmax, vhx, vhy, vx, vy, act);
+    }
+};
+
+// Load agent s's neighbours and build their half-planes into `rows`.  The
+// neighbour loads are issued eight at a time before those half-planes are
+// built, so one memory latency covers each group.  Neighbour ids are fetched
+// only when they are written out (the pair order comes with the entry).
+template <int KMAX, class Rows>
+__device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t id, float4 me,
                                                  const SceneDev &p, const float4 *__restrict__ sorted,
                                                  const int32_t *__restrict__ sid,
                                                  const int32_t *__restrict__ nbr, int32_t ld,
                                                  const int32_t *__restrict__ ncount,
                                                  int32_t *__restrict__ nbr_out, int32_t krow)
 {
+    constexpr int G = 8;
     const int32_t m = ncount[s];
     const double R = 2.0 * (double)p.radius;
     const double tau = (double)p.tau, dt = (double)p.dt;
     const double vix = (double)me.z, viy = (double)me.w;
-    int32_t e[KMAX];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) e[k] = k < m ? nbr[(int64_t)k * ld + s] : 0;
-    float4 o[KMAX];
+    for (int k0 = 0; k0 < KMAX; k0 += G) {
+        int32_t e[G];
+        float4 o[G];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-        o[k] = k < m ? sorted[e[k] & 0x7fffffff] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int u = 0; u < G; ++u)
+            e[u] = k0 + u < KMAX && k0 + u < m ? nbr[(int64_t)(k0 + u) * ld + s] : 0;
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        if (k < m) {
-            const double Px = (double)o[k].x - (double)me.x, Py = (double)o[k].y - (double)me.y;
-            const double Vx = vix - (double)o[k].z, Vy = viy - (double)o[k].w;
-            double ux, uy, nx, ny;
-            obstacle_exit(Px, Py, Vx, Vy, R, tau, dt, e[k] >= 0, ux, uy, nx, ny);
-            const double qx = vix + 0.5 * ux, qy = viy + 0.5 * uy;
-            L.n[k * kLpBlock] = make_double2(nx, ny);
-            L.b[k * kLpBlock] = nx * qx + ny * qy;
+        for (int u = 0; u < G; ++u)
+            o[u] = k0 + u < KMAX && k0 + u < m ? sorted[e[u] & 0x7fffffff]
+                                               : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int k = k0 + u;
+            if (k >= KMAX) continue;
+            double2 nk = make_double2(0.0, 0.0);
+            double bk = 0.0;
+            if (k < m) {
+                const double Px = (double)o[u].x - (double)me.x, Py = (double)o[u].y - (double)me.y;
+                const double Vx = vix - (double)o[u].z, Vy = viy - (double)o[u].w;
+                double ux, uy, nx, ny;
+                obstacle_exit(Px, Py, Vx, Vy, R, tau, dt, e[u] >= 0, ux, uy, nx, ny);
+                const double qx = vix + 0.5 * ux, qy = viy + 0.5 * uy;
+                nk = make_double2(nx, ny);
+                bk = nx * qx + ny * qy;
+            }
+            rows.set(k, nk, bk);
+            if (nbr_out && k < krow)
+                nbr_out[(int64_t)id * krow + k] = k < m ? sid[e[u] & 0x7fffffff] : -1;
         }
-    }
-    if (nbr_out) {
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-            if (k < krow) nbr_out[(int64_t)id * krow + k] = k < m ? sid[e[k] & 0x7fffffff] : -1;
     }
     return m;
 }
@@ -546,8 +593,9 @@ __device__ __forceinline__ void write_result(const OutArgs &o, float mex, float 
     if (o.status) o.status[id] = status;
 }
 
-// One lane per agent in cell order.  Feasible agents finish here; an agent
-// whose projection is empty is handed to the fallback list with everything
+// One lane per agent in cell order, half-planes in registers (LDS above 16
+// rows).  Feasible agents finish here; an agent whose projection is empty is
+// handed to the fallback list with everything
 // k_fallback needs (one atomic per wave): its record, its sort key (the failed
 // row) and its half-planes in stash slot `slot`.
 template <int KMAX, bool REC>
@@ -563,10 +611,12 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
                                                  double *__restrict__ stash_b,
                                                  Counters *__restrict__ counters)
 {
-    __shared__ double2 s_n[KMAX * kLpBlock];
-    __shared__ double s_b[KMAX * kLpBlock];
+    constexpr bool kRegs = KMAX <= kLpRegRows;
+    __shared__ double2 s_n[kRegs ? 1 : KMAX * kLpBlock];
+    __shared__ double s_b[kRegs ? 1 : KMAX * kLpBlock];
     const int32_t s = blockIdx.x * kLpBlock + threadIdx.x;
-    const Lane L{s_n + threadIdx.x, s_b + threadIdx.x};
+    LpRows<KMAX> rows;
+    if constexpr (!kRegs) rows.L = Lane{s_n + threadIdx.x, s_b + threadIdx.x};
     bool need_fb = false;
     FallbackItem it{};
     if (s < n) {
@@ -578,10 +628,10 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
         const double vmax = (double)p.vmax;
         double vx, vy;
         disc_clip(vmax, vhx, vhy, vx, vy);
-        const int m = build_constraints<KMAX>(L, s, id, me, p, sorted, sid, nbr, ld, ncount,
+        const int m = build_constraints<KMAX>(rows, s, id, me, p, sorted, sid, nbr, ld, ncount,
                                               out.nbr_out, out.krow);
         Active act;
-        const int fail = lp2_project<true>(L, m, 0, 0.0, vmax, vhx, vhy, vx, vy, &act);
+        const int fail = rows.project(m, vmax, vhx, vhy, vx, vy, &act);
         if (REC) out.tape_state[id] = me;
         if (fail < 0) {
             write_result(out, me.x, me.y, p.dt, id, n, vx, vy, vhx, vhy, 0);
@@ -628,9 +678,12 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
             fb_key[slot] = (uint8_t)it.fail;
             double2 *gn = stash_n + (int64_t)slot * kcap;
             double *gb = stash_b + (int64_t)slot * kcap;
-            for (int k = 0; k < it.m; ++k) {
-                gn[k] = L.N(k);
-                gb[k] = L.B(k);
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                if (k < it.m) {
+                    gn[k] = rows.N(k);
+                    gb[k] = rows.B(k);
+                }
             }
         }
     }

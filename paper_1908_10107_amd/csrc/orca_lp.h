@@ -226,6 +226,58 @@ ORCA_HD inline int lp2_project(const Lane &L, int m, int from, double relax, dou
     return -1;
 }
 
+// lp2_project from row 0 with no relaxation, for rows held in registers:
+// every loop runs to the compile-time bound KMAX (rows at or beyond m are
+// skipped), so all row indices are static and nothing goes to LDS.  Same
+// steps and arithmetic as lp2_project; the Active is always recorded.
+template <int KMAX>
+ORCA_HD inline int lp2_project_regs(const double2 (&n)[KMAX], const double (&b)[KMAX], int m,
+                                    double vmax, double vhx, double vhy, double &vx, double &vy,
+                                    Active *act)
+{
+    const double vm2 = vmax * vmax;
+    act->line = kLineNone;
+    act->src = kSrcFree;
+    int fail = -1;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        if (k >= m || fail >= 0) continue;
+        const double2 nk = n[k];
+        const double bk = b[k];
+        ORCA_COUNT(lp2_check);
+        if (nk.x * vx + nk.y * vy >= bk) continue;
+        ORCA_COUNT(lp2_line);
+        double h2 = vm2 - bk * bk;
+        if (h2 < 0.0) {
+            if (bk > 0.0) {
+                fail = k;  // the line misses the disc on the far side
+                continue;
+            }
+            h2 = 0.0;
+        }
+        Interval iv;
+        iv.init(sqrt(h2), 1.0);
+#pragma unroll
+        for (int j = 0; j < k; ++j) {
+            const double2 nj = n[j];
+            ORCA_COUNT(lp2_inner);
+            iv.add(nj.y * nk.x - nj.x * nk.y, b[j] - bk * (nj.x * nk.x + nj.y * nk.y), j);
+        }
+        if (iv.empty()) {
+            fail = k;
+            continue;
+        }
+        double tn, td;
+        const int src = iv.clamp(nk.x * vhy - nk.y * vhx, 1.0, tn, td);
+        const double t = tn / td;
+        vx = bk * nk.x - t * nk.y;
+        vy = bk * nk.y + t * nk.x;
+        act->line = k;
+        act->src = src;
+    }
+    return fail;
+}
+
 // Start of lp2_project: vhat, pulled radially into the disc.
 ORCA_HD inline void disc_clip(double vmax, double vhx, double vhy, double &vx, double &vy)
 {
