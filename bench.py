@@ -32,15 +32,16 @@ FP64_PEAK_TFLOPS = 78.6
 # Algorithmic work of each stage.
 #   binning (HBM): bbox 8 + key pass 28 + scatter 60 = 96 B per agent, + 12 B per cell.
 #   neighbours (HBM figure): own row 28 + list 4K + count 4 = 32 + 4K B per agent.
-#   half-planes + 2D LP (FP64 ALU): 29.2 K + 14.0 K operations per agent
-#     (half-plane construction and projection; 691 at K = 16).
-#   fallback (FP64 ALU): 40.75 K operations per fallback agent (652 at K = 16).
-# The FP64 operation counts were taken from the programs as written (each
-# multiply, add, fused multiply-add, divide or square root counts once) on a
-# dense evolved state; see the roofline section of the design notes.
+#   half-planes + 2D LP (FP64 ALU): 29.2 K + 15.2 K operations per agent
+#     (half-plane construction; projection and the choice of the fallback's
+#     first plane; 710 at K = 16).
+#   fallback (FP64 ALU): 28.2 K operations per fallback agent (451 at K = 16).
+# The FP64 operation counts were taken from the programs as written (an add,
+# subtract, multiply, divide or square root is one; a fused multiply-add two)
+# on a dense evolved state; see the roofline section of the design notes.
 HP_OPS_PER_K = 29.2
-LP2_OPS_PER_K = 14.0
-FB_OPS_PER_K = 40.75
+LP2_OPS_PER_K = 15.2
+FB_OPS_PER_K = 28.2
 
 
 def stage_roofline(stage: int, ms: float, n: int, k: int, cells: int, n_fallback: float):

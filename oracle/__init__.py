@@ -44,6 +44,12 @@ class HalfPlane(ctypes.Structure):
                 ("nx", ctypes.c_double), ("ny", ctypes.c_double)]
 
 
+class OracleAgents(ctypes.Structure):
+    """Per-agent radius, max speed and walking speed ([N] float32 or NULL each)."""
+    _fields_ = [("radius", ctypes.c_void_p), ("max_speed", ctypes.c_void_p),
+                ("pref_speed", ctypes.c_void_p)]
+
+
 _lib = None
 P = ctypes.c_void_p
 I64, I32, F32, F64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
@@ -86,6 +92,14 @@ def _ptr(a: Optional[np.ndarray]):
 
 def _f32(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _agents(radius=None, max_speed=None, pref_speed=None):
+    """(OracleAgents or None, arrays to keep alive) for optional per-agent properties."""
+    arrs = [_f32(a) for a in (radius, max_speed, pref_speed)]
+    if all(a is None for a in arrs):
+        return None, arrs
+    return ctypes.byref(OracleAgents(*[_ptr(a) for a in arrs])), arrs
 
 
 def params_array(params):
@@ -181,13 +195,15 @@ def knn_binned(pos, nd, k, lo=0, hi=None):
 # ---------------------------------------------------------------- whole state
 
 def velocities(pos, vel, pref, offsets, params, goals=None, agents=None, neighbor_mode=1,
-               radius=None):
+               radius=None, max_speed=None, pref_speed=None):
     """New velocities (float64) of ``agents`` (default: all) from one state.
 
-    Returns a dict with new_vel [M,2], vhat [M,2], nbr [M,kcap] (-1 padded),
-    n_nbr [M], status [M] (0 = 2D LP, 1 = fallback) and dstar [M].
+    radius, max_speed, pref_speed: optional per-agent values [N] in place of
+    the scene's.  Returns a dict with new_vel [M,2], vhat [M,2], nbr [M,kcap]
+    (-1 padded), n_nbr [M], status [M] (0 = 2D LP, 1 = fallback) and dstar [M].
     """
-    pos, vel, pref, goals, radius = map(_f32, (pos, vel, pref, goals, radius))
+    pos, vel, pref, goals = map(_f32, (pos, vel, pref, goals))
+    props, keep = _agents(radius, max_speed, pref_speed)
     n = pos.shape[1]
     offsets = np.ascontiguousarray(offsets, np.int64)
     pa = params_array(params)
@@ -201,22 +217,24 @@ def velocities(pos, vel, pref, offsets, params, goals=None, agents=None, neighbo
     out = dict(new_vel=np.zeros((m, 2)), vhat=np.zeros((m, 2)),
                nbr=np.full((m, kcap), -1, np.int64), n_nbr=np.zeros(m, np.int32),
                status=np.zeros(m, np.uint8), dstar=np.zeros(m))
-    lib().oracle_velocities(n, _ptr(pos), _ptr(vel), _ptr(pref), _ptr(goals), _ptr(radius),
+    lib().oracle_velocities(n, _ptr(pos), _ptr(vel), _ptr(pref), _ptr(goals), props,
                             len(params), _ptr(offsets), pa, _ptr(ag), m, neighbor_mode, kcap,
                             _ptr(out["new_vel"]), _ptr(out["vhat"]), _ptr(out["nbr"]),
                             _ptr(out["n_nbr"]), _ptr(out["status"]), _ptr(out["dstar"]))
     return out
 
 
-def step(pos, vel, pref, offsets, params, goals=None, n_steps=1, radius=None):
+def step(pos, vel, pref, offsets, params, goals=None, n_steps=1, radius=None, max_speed=None,
+         pref_speed=None):
     """Advance copies of the float32 state by ``n_steps``; returns (pos, vel, pref, status)."""
     pos = np.array(pos, np.float32, copy=True, order="C")
     vel = np.array(vel, np.float32, copy=True, order="C")
     pref = np.array(pref, np.float32, copy=True, order="C")
-    goals, radius = _f32(goals), _f32(radius)
+    goals = _f32(goals)
+    ag, keep = _agents(radius, max_speed, pref_speed)
     n = pos.shape[1]
     st = np.zeros(n, np.uint8)
-    lib().oracle_step(n, _ptr(pos), _ptr(vel), _ptr(pref), _ptr(goals), _ptr(radius),
+    lib().oracle_step(n, _ptr(pos), _ptr(vel), _ptr(pref), _ptr(goals), ag,
                       len(params), _ptr(np.ascontiguousarray(offsets, np.int64)),
                       params_array(params), int(n_steps), _ptr(st))
     return pos, vel, pref, st
@@ -227,11 +245,12 @@ def step(pos, vel, pref, offsets, params, goals=None, n_steps=1, radius=None):
 def _grad_lib():
     L = lib()
     if not hasattr(L, "_grad_ready"):
-        L.oracle_traj_loss.argtypes = [I64, P, P, P, I32, P, P, P, P, I32, P]
+        L.oracle_traj_loss.argtypes = [I64, P, P, P, I32, P, P, P, P, I32, P, P]
         L.oracle_traj_loss.restype = F64
-        L.oracle_traj_jvp.argtypes = [I64, P, P, P, I32, P, P, P, P, I32, P, P, P, P, I32, P, P]
+        L.oracle_traj_jvp.argtypes = [I64, P, P, P, I32, P, P, P, P, I32, P, P, P, P, I32, P, P,
+                                      P]
         L.oracle_traj_jvp.restype = None
-        L.oracle_step_jvp.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P]
+        L.oracle_step_jvp.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P]
         L.oracle_step_jvp.restype = None
         L.oracle_choice_jvp.argtypes = [ctypes.c_int] + [P] * 6 + [F64] * 13 + [P]
         L.oracle_choice_jvp.restype = ctypes.c_int
@@ -243,37 +262,45 @@ def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
 
 
-def traj_loss(pos0, vel0, pref, offsets, params, vmax, tau, n_steps, targets):
-    """L = sum |x(T) - y|^2 after n_steps float64 steps (fixed preferred velocities)."""
+def traj_loss(pos0, vel0, pref, offsets, params, vmax, tau, n_steps, targets, radius=None,
+              max_speed=None):
+    """L = sum |x(T) - y|^2 after n_steps float64 steps (fixed preferred velocities).
+
+    radius / max_speed: optional per-agent constants (a per-agent max speed
+    replaces the scene's leaf vmax for that agent)."""
     pos0, vel0, pref, targets, vmax, tau = map(_f64, (pos0, vel0, pref, targets, vmax, tau))
+    ag, keep = _agents(radius, max_speed, None)
     n = pos0.shape[1]
     return _grad_lib().oracle_traj_loss(n, _ptr(pos0), _ptr(vel0), _ptr(pref), len(params),
                                         _ptr(np.ascontiguousarray(offsets, np.int64)),
                                         params_array(params), _ptr(vmax), _ptr(tau), int(n_steps),
-                                        _ptr(targets))
+                                        _ptr(targets), ag)
 
 
 def traj_jvp(pos0, vel0, pref, offsets, params, vmax, tau, n_steps, targets, dpref, dvmax, dtau,
-             f32_state=False):
+             f32_state=False, radius=None, max_speed=None):
     """(L, dL) with dL the directional derivative along (dpref, dvmax, dtau), complex step.
 
     f32_state rounds the primal state to float32 after every step.
     """
     pos0, vel0, pref, targets, vmax, tau, dpref, dvmax, dtau = map(
         _f64, (pos0, vel0, pref, targets, vmax, tau, dpref, dvmax, dtau))
+    ag, keep = _agents(radius, max_speed, None)
     n = pos0.shape[1]
     L, dL = ctypes.c_double(), ctypes.c_double()
     _grad_lib().oracle_traj_jvp(n, _ptr(pos0), _ptr(vel0), _ptr(pref), len(params),
                                 _ptr(np.ascontiguousarray(offsets, np.int64)),
                                 params_array(params), _ptr(vmax), _ptr(tau), int(n_steps),
                                 _ptr(targets), _ptr(dpref), _ptr(dvmax), _ptr(dtau),
-                                int(bool(f32_state)), ctypes.byref(L), ctypes.byref(dL))
+                                int(bool(f32_state)), ag, ctypes.byref(L), ctypes.byref(dL))
     return L.value, dL.value
 
 
-def step_jvp(pos, vel, pref, offsets, params, dpos, dvel, dpref, dvmax, dtau):
+def step_jvp(pos, vel, pref, offsets, params, dpos, dvel, dpref, dvmax, dtau, radius=None,
+             max_speed=None):
     """Tangent (dpos', dvel') of one float64 step from the float32 state (complex step)."""
     pos, vel, pref = map(_f32, (pos, vel, pref))
+    ag, keep = _agents(radius, max_speed, None)
     dpos, dvel, dpref, dvmax, dtau = map(_f64, (dpos, dvel, dpref, dvmax, dtau))
     n = pos.shape[1]
     op = np.zeros((2, n))
@@ -281,5 +308,5 @@ def step_jvp(pos, vel, pref, offsets, params, dpos, dvel, dpref, dvmax, dtau):
     _grad_lib().oracle_step_jvp(n, _ptr(pos), _ptr(vel), _ptr(pref), len(params),
                                 _ptr(np.ascontiguousarray(offsets, np.int64)),
                                 params_array(params), _ptr(dpos), _ptr(dvel), _ptr(dpref),
-                                _ptr(dvmax), _ptr(dtau), _ptr(op), _ptr(ov))
+                                _ptr(dvmax), _ptr(dtau), ag, _ptr(op), _ptr(ov))
     return op, ov

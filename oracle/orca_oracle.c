@@ -60,6 +60,31 @@ typedef struct {
     int32_t max_neighbors, pad;
 } oracle_params;
 
+/*
+ * Optional per-agent properties (section 4, the crossing whose people differ
+ * in size and speed): radius, max speed and walking speed, each an array over
+ * all agents or NULL for the scene's value.  A pair's combined radius is
+ * r_i + r_j.
+ */
+typedef struct {
+    const float *radius, *max_speed, *pref_speed;
+} oracle_agents;
+
+static double ag_radius(const oracle_agents *ag, const oracle_params *p, int64_t i)
+{
+    return ag && ag->radius ? (double)ag->radius[i] : (double)p->radius;
+}
+
+static double ag_vmax(const oracle_agents *ag, const oracle_params *p, int64_t i)
+{
+    return ag && ag->max_speed ? (double)ag->max_speed[i] : (double)p->max_speed;
+}
+
+static double ag_speed(const oracle_agents *ag, const oracle_params *p, int64_t i)
+{
+    return ag && ag->pref_speed ? (double)ag->pref_speed[i] : (double)p->pref_speed;
+}
+
 
 /* Threads the parallel loops use. */
 int oracle_threads(void)
@@ -290,8 +315,9 @@ void oracle_steer(double px, double py, double gx, double gy, double s, double d
  * New velocity of agent i given its neighbour list.  Writes the half-planes
  * (if hp_out), returns status 0 (2D LP feasible) or 1 (fallback).
  */
-int oracle_agent_velocity(int64_t n_total, const float *pos, const float *vel, const float *rad,
-                          const oracle_params *p, int64_t i, int32_t m, const int64_t *nbr,
+int oracle_agent_velocity(int64_t n_total, const float *pos, const float *vel,
+                          const oracle_agents *ag, const oracle_params *p, int64_t i, int32_t m,
+                          const int64_t *nbr,
                           double vhx, double vhy, double *ox, double *oy, double *dstar,
                           halfplane *hp_out, int32_t *branch_out)
 {
@@ -306,13 +332,11 @@ int oracle_agent_velocity(int64_t n_total, const float *pos, const float *vel, c
         Py[t] = (double)y[j] - (double)y[i];
         Vx[t] = (double)vx[i] - (double)vx[j];
         Vy[t] = (double)vy[i] - (double)vy[j];
-        double ri = rad ? (double)rad[i] : (double)p->radius;
-        double rj = rad ? (double)rad[j] : (double)p->radius;
-        Rs[t] = ri + rj;
+        Rs[t] = ag_radius(ag, p, i) + ag_radius(ag, p, j);
         first[t] = i < j;
     }
     return choose(m, Px, Py, Vx, Vy, Rs, first, (double)vx[i], (double)vy[i], p->time_horizon,
-                  p->dt, p->max_speed, vhx, vhy, ox, oy, dstar, hp_out ? hp_out : hbuf,
+                  p->dt, ag_vmax(ag, p, i), vhx, vhy, ox, oy, dstar, hp_out ? hp_out : hbuf,
                   branch_out);
 }
 
@@ -368,7 +392,7 @@ static int scene_of(int32_t n_scenes, const int64_t *off, int64_t i)
  * nbr [n_agents,kcap] (-1 padded), n_nbr, status, dstar.
  */
 void oracle_velocities(int64_t n_total, const float *pos, const float *vel, const float *pref,
-                       const float *goals, const float *rad, int32_t n_scenes,
+                       const float *goals, const oracle_agents *ag, int32_t n_scenes,
                        const int64_t *offsets, const oracle_params *params,
                        const int64_t *agents, int64_t n_agents, int32_t neighbor_mode,
                        int32_t kcap, double *new_vel, double *vhat, int64_t *nbr,
@@ -396,14 +420,14 @@ void oracle_velocities(int64_t n_total, const float *pos, const float *vel, cons
                                  p->max_neighbors, ids, NULL);
         double vhx, vhy;
         if (goals)
-            oracle_steer(pos[i], pos[n_total + i], goals[i], goals[n_total + i], p->pref_speed,
-                         p->dt, &vhx, &vhy);
+            oracle_steer(pos[i], pos[n_total + i], goals[i], goals[n_total + i],
+                         ag_speed(ag, p, i), p->dt, &vhx, &vhy);
         else {
             vhx = pref[i];
             vhy = pref[n_total + i];
         }
         double ox, oy, d;
-        int st = oracle_agent_velocity(n_total, pos, vel, rad, p, i, m, ids, vhx, vhy, &ox, &oy,
+        int st = oracle_agent_velocity(n_total, pos, vel, ag, p, i, m, ids, vhx, vhy, &ox, &oy,
                                        &d, NULL, NULL);
         new_vel[2 * a] = ox;
         new_vel[2 * a + 1] = oy;
@@ -427,13 +451,13 @@ void oracle_velocities(int64_t n_total, const float *pos, const float *vel, cons
  * step (and written to pref); without, pref is held fixed.
  */
 void oracle_step(int64_t n_total, float *pos, float *vel, float *pref, const float *goals,
-                 const float *rad, int32_t n_scenes, const int64_t *offsets,
+                 const oracle_agents *ag, int32_t n_scenes, const int64_t *offsets,
                  const oracle_params *params, int32_t n_steps, uint8_t *status_last)
 {
     double *nv = (double *)malloc(sizeof(double) * 2 * (size_t)n_total);
     double *vh = (double *)malloc(sizeof(double) * 2 * (size_t)n_total);
     for (int32_t step = 0; step < n_steps; ++step) {
-        oracle_velocities(n_total, pos, vel, pref, goals, rad, n_scenes, offsets, params, NULL,
+        oracle_velocities(n_total, pos, vel, pref, goals, ag, n_scenes, offsets, params, NULL,
                           n_total, 1, 1, nv, vh, NULL, NULL,
                           step == n_steps - 1 ? status_last : NULL, NULL);
         for (int64_t i = 0; i < n_total; ++i) {
@@ -466,7 +490,7 @@ void oracle_step(int64_t n_total, float *pos, float *vel, float *pref, const flo
 #define DEFINE_TRAJ_STEP(R_T, SUF, RE_, FIRST_CHOOSE)                                           \
     static void traj_step##SUF(int64_t n, R_T *pos, R_T *vel, const R_T *pref, int32_t n_scenes,  \
                                const int64_t *off, const oracle_params *par, const R_T *vmax_s,   \
-                               const R_T *tau_s)                                                  \
+                               const R_T *tau_s, const oracle_agents *ag)                         \
     {                                                                                             \
         float *p32 = (float *)malloc(sizeof(float) * 2 * (size_t)(n ? n : 1));                   \
         R_T *nv = (R_T *)malloc(sizeof(R_T) * 2 * (size_t)(n ? n : 1));                           \
@@ -489,9 +513,11 @@ void oracle_step(int64_t n_total, float *pos, float *vel, float *pref, const flo
                 Py[t] = pos[n + j] - pos[n + i];                                                  \
                 Vx[t] = vel[i] - vel[j];                                                          \
                 Vy[t] = vel[n + i] - vel[n + j];                                                  \
-                Rs[t] = 2.0 * (double)p->radius;                                                  \
+                Rs[t] = ag_radius(ag, p, i) + ag_radius(ag, p, j);                                \
                 first[t] = i < j;                                                                 \
             }                                                                                     \
+            /* a per-agent max speed is a constant; the scene's is the leaf */                    \
+            const R_T vmax_i = ag && ag->max_speed ? (R_T)ag->max_speed[i] : vmax_s[s];           \
             FIRST_CHOOSE;                                                                         \
         }                                                                                         \
         for (int64_t i = 0; i < n; ++i) {                                                         \
@@ -509,13 +535,13 @@ void oracle_step(int64_t n_total, float *pos, float *vel, float *pref, const flo
 
 DEFINE_TRAJ_STEP(double, _d, (double), {
     halfplane hb[64];
-    choose(m, Px, Py, Vx, Vy, Rs, first, vel[i], vel[n + i], tau_s[s], p->dt, vmax_s[s], pref[i],
+    choose(m, Px, Py, Vx, Vy, Rs, first, vel[i], vel[n + i], tau_s[s], p->dt, vmax_i, pref[i],
            pref[n + i], &nv[2 * i], &nv[2 * i + 1], NULL, hb, NULL);
 })
 
 DEFINE_TRAJ_STEP(double complex, _c, creal, {
     halfplane_t_cx hb[64];
-    choose_cx(m, Px, Py, Vx, Vy, Rs, first, vel[i], vel[n + i], tau_s[s], p->dt, vmax_s[s],
+    choose_cx(m, Px, Py, Vx, Vy, Rs, first, vel[i], vel[n + i], tau_s[s], p->dt, vmax_i,
               pref[i], pref[n + i], &nv[2 * i], &nv[2 * i + 1], NULL, hb, NULL);
 })
 
@@ -527,14 +553,14 @@ DEFINE_TRAJ_STEP(double complex, _c, creal, {
 double oracle_traj_loss(int64_t n, const double *pos0, const double *vel0, const double *pref,
                         int32_t n_scenes, const int64_t *off, const oracle_params *par,
                         const double *vmax_s, const double *tau_s, int32_t n_steps,
-                        const double *targets)
+                        const double *targets, const oracle_agents *ag)
 {
     double *pos = (double *)malloc(sizeof(double) * 2 * (size_t)n);
     double *vel = (double *)malloc(sizeof(double) * 2 * (size_t)n);
     memcpy(pos, pos0, sizeof(double) * 2 * (size_t)n);
     memcpy(vel, vel0, sizeof(double) * 2 * (size_t)n);
     for (int32_t t = 0; t < n_steps; ++t)
-        traj_step_d(n, pos, vel, pref, n_scenes, off, par, vmax_s, tau_s);
+        traj_step_d(n, pos, vel, pref, n_scenes, off, par, vmax_s, tau_s, ag);
     double L = 0.0;
     for (int64_t i = 0; i < 2 * n; ++i) L += (pos[i] - targets[i]) * (pos[i] - targets[i]);
     free(pos);
@@ -552,7 +578,8 @@ void oracle_traj_jvp(int64_t n, const double *pos0, const double *vel0, const do
                      int32_t n_scenes, const int64_t *off, const oracle_params *par,
                      const double *vmax_s, const double *tau_s, int32_t n_steps,
                      const double *targets, const double *dpref, const double *dvmax,
-                     const double *dtau, int32_t f32_state, double *loss, double *dloss)
+                     const double *dtau, int32_t f32_state, const oracle_agents *ag,
+                     double *loss, double *dloss)
 {
     const double h = 1e-30;
     double complex *pos = (double complex *)malloc(sizeof(double complex) * 2 * (size_t)n);
@@ -570,7 +597,7 @@ void oracle_traj_jvp(int64_t n, const double *pos0, const double *vel0, const do
         ta[s] = tau_s[s] + I * h * (dtau ? dtau[s] : 0.0);
     }
     for (int32_t t = 0; t < n_steps; ++t) {
-        traj_step_c(n, pos, vel, pr, n_scenes, off, par, vm, ta);
+        traj_step_c(n, pos, vel, pr, n_scenes, off, par, vm, ta, ag);
         if (f32_state) /* keep the primal on float32 states (as the GPU stores them) */
             for (int64_t i = 0; i < 2 * n; ++i) {
                 pos[i] = (double)(float)creal(pos[i]) + I * cimag(pos[i]);
@@ -596,7 +623,8 @@ void oracle_traj_jvp(int64_t n, const double *pos0, const double *vel0, const do
 void oracle_step_jvp(int64_t n, const float *pos, const float *vel, const float *pref,
                      int32_t n_scenes, const int64_t *off, const oracle_params *par,
                      const double *dpos, const double *dvel, const double *dpref,
-                     const double *dvmax, const double *dtau, double *dpos_out, double *dvel_out)
+                     const double *dvmax, const double *dtau, const oracle_agents *ag,
+                     double *dpos_out, double *dvel_out)
 {
     const double h = 1e-30;
     double complex *p = (double complex *)malloc(sizeof(double complex) * 2 * (size_t)n);
@@ -613,7 +641,7 @@ void oracle_step_jvp(int64_t n, const float *pos, const float *vel, const float 
         vm[s] = (double)par[s].max_speed + I * h * dvmax[s];
         ta[s] = (double)par[s].time_horizon + I * h * dtau[s];
     }
-    traj_step_c(n, p, v, pr, n_scenes, off, par, vm, ta);
+    traj_step_c(n, p, v, pr, n_scenes, off, par, vm, ta, ag);
     for (int64_t i = 0; i < 2 * n; ++i) {
         dpos_out[i] = cimag(p[i]) / h;
         dvel_out[i] = cimag(v[i]) / h;

@@ -597,7 +597,7 @@ __device__ __forceinline__ void write_result(const OutArgs &o, float mex, float 
 // rows).  Feasible agents finish here; an agent whose projection is empty is
 // handed to the fallback list with everything
 // k_fallback needs (one atomic per wave): its record, its sort key (the failed
-// row) and its half-planes in stash slot `slot`.
+// row) and its half-planes in stash slot `slot`, in stash_position order.
 template <int KMAX, bool REC>
 __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sorted,
                                                  const int32_t *__restrict__ sid,
@@ -653,6 +653,21 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
             it.fail = (int8_t)fail;
             it.line = (int8_t)act.line;
             it.src = (int8_t)act.src;
+            // the most violated row from the failed one on, at the last optimum
+            int worst = fail;
+            double wv = -1.0e300;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                if (k >= fail && k < m) {
+                    const double2 nk = rows.N(k);
+                    const double viol = rows.B(k) - (nk.x * vx + nk.y * vy);
+                    if (viol > wv) {
+                        wv = viol;
+                        worst = k;
+                    }
+                }
+            }
+            it.worst = (int8_t)worst;
             it.vx = vx;
             it.vy = vy;
             it.vhx = vhx;
@@ -681,8 +696,9 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
                 if (k < it.m) {
-                    gn[k] = rows.N(k);
-                    gb[k] = rows.B(k);
+                    const int q = stash_position(k, it);
+                    gn[q] = rows.N(k);
+                    gb[q] = rows.B(k);
                 }
             }
         }
@@ -735,63 +751,117 @@ __global__ __launch_bounds__(kFbSortBlock) void k_fb_sort(const uint8_t *__restr
     }
 }
 
-// Exchange rows a and b of a lane's constraint column (and, when recording,
-// of its column of original row indices).
-template <bool REC>
-__device__ __forceinline__ void swap_rows(const Lane &L, int8_t *idx, int a, int b)
+// Rows of k_fallback: up to 16 in registers, read with wave-uniform indices
+// only (every loop of the programs runs over fixed bounds), more in a per-lane
+// LDS column.
+template <int KMAX, bool IN_REGS = (KMAX <= kLpRegRows)>
+struct FbRows;
+template <int KMAX>
+struct FbRows<KMAX, true> {
+    // references to three local arrays of doubles of the kernel: arrays of
+    // their own (not members of a struct, not double2) are kept in registers
+    double (&nx)[KMAX];
+    double (&ny)[KMAX];
+    double (&b)[KMAX];
+    __device__ __forceinline__ double2 N(int k) const { return make_double2(nx[k], ny[k]); }
+    __device__ __forceinline__ double B(int k) const { return b[k]; }
+    __device__ __forceinline__ void set(int k, double2 nk, double bk)
+    {
+        nx[k] = nk.x;
+        ny[k] = nk.y;
+        b[k] = bk;
+    }
+};
+template <int KMAX>
+struct FbRows<KMAX, false> {
+    Lane L;
+    __device__ __forceinline__ double2 N(int k) const { return L.N(k); }
+    __device__ __forceinline__ double B(int k) const { return L.B(k); }
+    __device__ __forceinline__ void set(int k, double2 nk, double bk)
+    {
+        L.n[k * kLpStride] = nk;
+        L.b[k * kLpStride] = bk;
+    }
+};
+
+// The persistent loop of k_fallback over its share of the sorted list.
+template <int KMAX, bool REC, class RS>
+__device__ __forceinline__ void fallback_items(RS &rows, const OutArgs &out, int32_t n, int32_t kcap,
+                                               const FallbackItem *__restrict__ fb_list,
+                                               const int32_t *__restrict__ fb_order,
+                                               const double2 *__restrict__ stash_n,
+                                               const double *__restrict__ stash_b, uint32_t count)
 {
-    if (a == b) return;
-    const double2 na = L.N(a), nb = L.N(b);
-    const double ba = L.B(a), bb = L.B(b);
-    L.n[a * kLpStride] = nb;
-    L.n[b * kLpStride] = na;
-    L.b[a * kLpStride] = bb;
-    L.b[b * kLpStride] = ba;
-    if (REC) {
-        const int8_t t = idx[a * kLpStride];
-        idx[a * kLpStride] = idx[b * kLpStride];
-        idx[b * kLpStride] = t;
+    for (uint32_t q = blockIdx.x * kLpBlock + threadIdx.x; q < count; q += gridDim.x * kLpBlock) {
+        const int32_t slot = fb_order[q];
+        const FallbackItem it = fb_list[slot];
+        const int m = it.m, fail = it.fail;
+        const double2 *gn = stash_n + (int64_t)slot * kcap;
+        const double *gb = stash_b + (int64_t)slot * kcap;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if (k < m) rows.set(k, gn[k], gb[k]);
+            else rows.set(k, make_double2(0.0, 0.0), 0.0);
+        }
+        const double vmax = (double)it.vmax;
+        double vx = it.vx, vy = it.vy;
+        int plane = -1;
+        Active dact;
+        const double d = lp3_least_penetration<KMAX>(rows, m, fail, vmax, vx, vy, &plane, &dact);
+        FrontRows F;
+        F.pos[0] = plane;
+        F.pos[1] = dact.line;
+        F.pos[2] = dact.src;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            F.n[u] = make_double2(0.0, 0.0);
+            F.b[u] = 0.0;
+            if (F.pos[u] < 0) F.pos[u] = -1;
+        }
+        // copy the rows that fix d*: one pass with the same row index on every
+        // lane (a per-lane index would move register-held rows to memory)
+#pragma unroll 1
+        for (int k = 0; k < KMAX; ++k) {
+            const double2 nk = rows.N(k);
+            const double bk = rows.B(k);
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                if (F.pos[u] == k) {
+                    F.n[u] = nk;
+                    F.b[u] = bk;
+                }
+            }
+        }
+        double wx, wy;
+        Active ract;
+        const bool ok = lp2_project_front<KMAX>(rows, m, F, d + kRelax, vmax, it.vhx, it.vhy, wx,
+                                                wy, &ract) < 0;
+        if (ok) {
+            vx = wx;
+            vy = wy;
+        }
+        if (REC) {
+            TapeCode tc{};
+            tc.status = 1;
+            tc.p_line = (int8_t)stash_row(ract.line, it);
+            tc.p_src = (int8_t)stash_row(ract.src, it);
+            tc.d_plane = (int8_t)stash_row(plane, it);
+            tc.d_line = (int8_t)stash_row(dact.line, it);
+            tc.d_src = (int8_t)stash_row(dact.src, it);
+            tc.relaxed_empty = ok ? 0 : 1;
+            tc.dstar = d;
+            out.tape_codes[it.id] = tc;
+        }
+        write_result(out, it.mex, it.mey, it.dt, it.id, n, vx, vy, it.vhx, it.vhy, 1);
     }
 }
 
-// Move up to three distinct rows (negative entries are not rows) to the front,
-// in the order given.
-template <bool REC>
-__device__ __forceinline__ void rows_to_front(const Lane &L, int8_t *idx, int r0, int r1, int r2)
-{
-    int p = 0;
-    if (r0 >= 0) {
-        swap_rows<REC>(L, idx, p, r0);
-        if (r1 == p) r1 = r0;
-        if (r2 == p) r2 = r0;
-        ++p;
-    }
-    if (r1 >= 0) {
-        swap_rows<REC>(L, idx, p, r1);
-        if (r2 == p) r2 = r1;
-        ++p;
-    }
-    if (r2 >= 0) swap_rows<REC>(L, idx, p, r2);
-}
-
-// Original row of a recorded row position (negative codes pass through).
-__device__ __forceinline__ int8_t orig_row(const int8_t *idx, int r)
-{
-    return r >= 0 ? idx[r * kLpStride] : (int8_t)r;
-}
-
-// Persistent over the fallback list in sorted order.  The programs' results
-// do not depend on the order of their rows, only their cost does, so rows are
-// moved first:
-//   * the rows that fix the projection's last optimum to the front of the
-//     rows before the failed one, and the most violated of the rest to the
-//     failed position: the least-penetration program then meets few
-//     violations after its first plane;
-//   * after it, the rows that fix d* to the front: the relaxed projection's
-//     optimum lies where they cross, so later rows are rarely violated.
-// Then d* from the projection's last optimum (the rows before the failed one
-// hold there with t = 0), and the point closest to vhat among those within
-// d* + delta of every half-plane.
+// Persistent over the fallback list in sorted order.  The rows come in stash
+// order (stash_position): d* from the projection's last optimum (the rows
+// before the failed one hold there with t = 0), then the point closest to
+// vhat among those within d* + delta of every half-plane, with the rows that
+// fix d* taken first: the relaxed projection's optimum lies where they cross,
+// so the other rows are rarely violated.
 template <int KMAX, bool REC>
 __global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, int32_t kcap,
                                                        const FallbackItem *__restrict__ fb_list,
@@ -800,68 +870,17 @@ __global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, i
                                                        const double *__restrict__ stash_b,
                                                        const Counters *__restrict__ counters)
 {
-    __shared__ double2 s_n[KMAX * kLpBlock];
-    __shared__ double s_b[KMAX * kLpBlock];
-    __shared__ int8_t s_idx[REC ? KMAX * kLpBlock : 1];
+    constexpr bool kRegs = KMAX <= kLpRegRows;
+    __shared__ double2 s_n[kRegs ? 1 : KMAX * kLpBlock];
+    __shared__ double s_b[kRegs ? 1 : KMAX * kLpBlock];
     const uint32_t count = counters->n_fallback;
-    const Lane L{s_n + threadIdx.x, s_b + threadIdx.x};
-    int8_t *idx_col = REC ? s_idx + threadIdx.x : s_idx;
-    for (uint32_t q = blockIdx.x * kLpBlock + threadIdx.x; q < count; q += gridDim.x * kLpBlock) {
-        const int32_t slot = fb_order[q];
-        const FallbackItem it = fb_list[slot];
-        const int m = it.m, fail = it.fail;
-        const double2 *gn = stash_n + (int64_t)slot * kcap;
-        const double *gb = stash_b + (int64_t)slot * kcap;
-        double vx = it.vx, vy = it.vy;
-        int worst = fail;
-        double wv = -1.0e300;
-        for (int k = 0; k < m; ++k) {
-            const double2 nk = gn[k];
-            const double bk = gb[k];
-            L.n[k * kLpStride] = nk;
-            L.b[k * kLpStride] = bk;
-            if (REC) idx_col[k * kLpStride] = (int8_t)k;
-            const double viol = bk - (nk.x * vx + nk.y * vy);
-            if (k >= fail && viol > wv) {
-                wv = viol;
-                worst = k;
-            }
-        }
-        swap_rows<REC>(L, idx_col, fail, worst);
-        rows_to_front<REC>(L, idx_col, it.line, it.src, -1);
-        const double vmax = (double)it.vmax;
-        int plane = -1;
-        Active dact;
-        const double d = lp3_least_penetration<true>(L, m, fail, vmax, vx, vy, &plane, &dact);
-        int8_t d_plane = 0, d_line = 0, d_src = 0;
-        if (REC) {
-            d_plane = orig_row(idx_col, plane);
-            d_line = orig_row(idx_col, dact.line);
-            d_src = orig_row(idx_col, dact.src);
-        }
-        rows_to_front<REC>(L, idx_col, plane, dact.line, dact.src);
-        double wx, wy;
-        disc_clip(vmax, it.vhx, it.vhy, wx, wy);
-        Active ract;
-        const bool ok =
-            lp2_project<REC>(L, m, 0, d + kRelax, vmax, it.vhx, it.vhy, wx, wy, &ract) < 0;
-        if (ok) {
-            vx = wx;
-            vy = wy;
-        }
-        if (REC) {
-            TapeCode tc{};
-            tc.status = 1;
-            tc.p_line = orig_row(idx_col, ract.line);
-            tc.p_src = orig_row(idx_col, ract.src);
-            tc.d_plane = d_plane;
-            tc.d_line = d_line;
-            tc.d_src = d_src;
-            tc.relaxed_empty = ok ? 0 : 1;
-            tc.dstar = d;
-            out.tape_codes[it.id] = tc;
-        }
-        write_result(out, it.mex, it.mey, it.dt, it.id, n, vx, vy, it.vhx, it.vhy, 1);
+    double rnx[kRegs ? KMAX : 1], rny[kRegs ? KMAX : 1], rb[kRegs ? KMAX : 1];
+    if constexpr (kRegs) {
+        FbRows<KMAX> rows{rnx, rny, rb};
+        fallback_items<KMAX, REC>(rows, out, n, kcap, fb_list, fb_order, stash_n, stash_b, count);
+    } else {
+        FbRows<KMAX> rows{Lane{s_n + threadIdx.x, s_b + threadIdx.x}};
+        fallback_items<KMAX, REC>(rows, out, n, kcap, fb_list, fb_order, stash_n, stash_b, count);
     }
 }
 

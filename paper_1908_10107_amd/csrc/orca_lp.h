@@ -24,6 +24,9 @@ struct double2 {
 inline double2 make_double2(double x, double y) { return double2{x, y}; }
 #endif
 
+// Always inlined: a row store held in registers must not escape into a call.
+#define ORCA_HDI ORCA_HD __attribute__((always_inline))
+
 // Work-counting hook for offline analysis builds; compiles to nothing here.
 #ifndef ORCA_COUNT
 #define ORCA_COUNT(what)
@@ -131,7 +134,7 @@ struct Interval {
     double lo_n, lo_d, hi_n, hi_d;
     int lo_src, hi_src;
     bool bad;
-    ORCA_HD inline void init(double h_n, double h_d)
+    ORCA_HDI inline void init(double h_n, double h_d)
     {
         lo_n = -h_n;
         lo_d = h_d;
@@ -142,7 +145,7 @@ struct Interval {
         bad = false;
     }
     // add s * den >= num (row src)
-    ORCA_HD inline void add(double den, double num, int src)
+    ORCA_HDI inline void add(double den, double num, int src)
     {
         const bool up = den > 0.0, down = den < 0.0;
         const bool raise = up && num * lo_d > lo_n * den;
@@ -155,10 +158,10 @@ struct Interval {
         hi_src = lower ? src : hi_src;
         bad = bad | (!up & !down & (num > 0.0));
     }
-    ORCA_HD inline bool empty() const { return bad || lo_n * hi_d > hi_n * lo_d; }
+    ORCA_HDI inline bool empty() const { return bad || lo_n * hi_d > hi_n * lo_d; }
     // t_n / t_d clamped into the interval (t_d > 0); returns the source that
     // bounds the result (kSrcFree if t was inside)
-    ORCA_HD inline int clamp(double t_n, double t_d, double &o_n, double &o_d) const
+    ORCA_HDI inline int clamp(double t_n, double t_d, double &o_n, double &o_d) const
     {
         if (t_n * lo_d < lo_n * t_d) {
             o_n = lo_n;
@@ -279,7 +282,7 @@ ORCA_HD inline int lp2_project_regs(const double2 (&n)[KMAX], const double (&b)[
 }
 
 // Start of lp2_project: vhat, pulled radially into the disc.
-ORCA_HD inline void disc_clip(double vmax, double vhx, double vhy, double &vx, double &vy)
+ORCA_HDI inline void disc_clip(double vmax, double vhx, double vhy, double &vx, double &vy)
 {
     const double vh2 = vhx * vhx + vhy * vhy;
     if (vh2 > vmax * vmax) {
@@ -292,11 +295,18 @@ ORCA_HD inline void disc_clip(double vmax, double vhx, double vhy, double &vx, d
     }
 }
 
+// The fallback's programs below take a row store RS (N(k), B(k)) and a
+// compile-time bound KB on the number of rows.  Every loop counter runs over
+// fixed bounds and is the same for all lanes of a wave (a lane outside its own
+// range just skips the body), so a store that keeps the rows in registers is
+// indexed with a wave-uniform index, and nothing returns early.
+
 // Projected constraint i of the plane-k subproblem: i = -1 is "no negative
 // penetration" (-n_k . v >= -b_k), i >= 0 is "constraint i penetrates no more
 // than k" ((n_i - n_k) . v >= b_i - b_k).
-ORCA_HD inline void plane_row(const Lane &L, int i, double2 nk, double bk, double &mx,
-                              double &my, double &c)
+template <class RS>
+ORCA_HDI inline void plane_row(const RS &L, int i, double2 nk, double bk, double &mx, double &my,
+                              double &c)
 {
     if (i < 0) {
         mx = -nk.x;
@@ -314,20 +324,21 @@ ORCA_HD inline void plane_row(const Lane &L, int i, double2 nk, double bk, doubl
 // (incremental, as lp2_project but with a linear objective).  Line i is
 // p(s) = c_i m_i / |m_i|^2 + s (-m_i.y, m_i.x); each constraint j on it is
 // multiplied through by |m_i|^2 > 0 so no division is needed until the end.
-// Returns false if the subproblem is empty.  With REC the last line and its
-// bound go to *act (line kLineNone: the start point vmax n_k stands).
-template <bool REC>
-ORCA_HD inline bool lp2_plane(const Lane &L, int k, double2 nk, double bk, double vmax,
-                              double &vx, double &vy, Active *act)
+// Returns false if the subproblem is empty.  The last line and its bound go
+// to *act (line kLineNone: the start point vmax n_k stands).  k is the same on
+// every lane that calls it together.
+template <class RS>
+ORCA_HDI inline bool lp2_plane(const RS &L, int k, double2 nk, double bk, double vmax, double &vx,
+                              double &vy, Active *act)
 {
     const double vm2 = vmax * vmax;
     vx = vmax * nk.x;
     vy = vmax * nk.y;
-    if (REC) {
-        act->line = kLineNone;
-        act->src = kSrcDisc;
-    }
+    act->line = kLineNone;
+    act->src = kSrcDisc;
+    bool ok = true;
     for (int i = -1; i < k; ++i) {
+        if (!ok) continue;
         double mx, my, ci;
         plane_row(L, i, nk, bk, mx, my, ci);
         ORCA_COUNT(plane_check);
@@ -335,11 +346,14 @@ ORCA_HD inline bool lp2_plane(const Lane &L, int k, double2 nk, double bk, doubl
         ORCA_COUNT(plane_line);
         const double mm = mx * mx + my * my;
         if (mm == 0.0) {
-            if (ci > 0.0) return false;
+            ok = !(ci > 0.0);
             continue;
         }
         const double disc = vm2 * mm - ci * ci;
-        if (disc < 0.0) return false;
+        if (disc < 0.0) {
+            ok = false;
+            continue;
+        }
         // s in [-sqrt(disc), sqrt(disc)] / mm
         Interval iv;
         iv.init(sqrt(disc), mm);
@@ -350,7 +364,10 @@ ORCA_HD inline bool lp2_plane(const Lane &L, int k, double2 nk, double bk, doubl
             // a.(c_i m / mm + s d) >= c_j  ->  s (a.d) mm >= c_j mm - c_i (a.m)
             iv.add((ay * mx - ax * my) * mm, cj * mm - ci * (ax * mx + ay * my), j);
         }
-        if (iv.empty()) return false;
+        if (iv.empty()) {
+            ok = false;
+            continue;
+        }
         const double slope = nk.y * mx - nk.x * my;  // n_k . (-my, mx)
         double sn, sd;
         int src;
@@ -369,31 +386,28 @@ ORCA_HD inline bool lp2_plane(const Lane &L, int k, double2 nk, double bk, doubl
         const double c0 = ci / mm;
         vx = c0 * mx - s * my;
         vy = c0 * my + s * mx;
-        if (REC) {
-            act->line = i;
-            act->src = src;
-        }
+        act->line = i;
+        act->src = src;
     }
-    return true;
+    return ok;
 }
 
 // Least penetration d* = min over the disc of max_k (b_k - n_k . v), by an
 // incremental 3D program in (v, t) with t >= 0, starting from a point that
-// satisfies constraints 0..start-1 (so t = 0 is optimal for them).  When
-// constraint k is violated beyond the current t, the new optimum has
-// t = b_k - n_k . v: maximise n_k . v on that plane.  With REC the plane of
-// the last accepted step (-1: none) and its program's Active are recorded.
-template <bool REC>
-ORCA_HD inline double lp3_least_penetration(const Lane &L, int m, int start, double vmax,
-                                            double &vx, double &vy, int *plane, Active *act)
+// satisfies rows 0..start-1 (so t = 0 is optimal for them).  When row k is
+// violated beyond the current t, the new optimum has t = b_k - n_k . v:
+// maximise n_k . v on that plane.  The plane of the last accepted step (-1:
+// none) and its program's Active are recorded.
+template <int KB, class RS>
+ORCA_HDI inline double lp3_least_penetration(const RS &L, int m, int start, double vmax, double &vx,
+                                            double &vy, int *plane, Active *act)
 {
     double t = 0.0;
-    if (REC) {
-        *plane = -1;
-        act->line = kLineNone;
-        act->src = kSrcDisc;
-    }
-    for (int k = start; k < m; ++k) {
+    *plane = -1;
+    act->line = kLineNone;
+    act->src = kSrcDisc;
+    for (int k = 0; k < KB; ++k) {
+        if (k < start || k >= m) continue;
         const double2 nk = L.N(k);
         const double bk = L.B(k);
         ORCA_COUNT(lp3_check);
@@ -401,17 +415,94 @@ ORCA_HD inline double lp3_least_penetration(const Lane &L, int m, int start, dou
         ORCA_COUNT(lp3_plane);
         double wx, wy;
         Active pa;
-        if (lp2_plane<REC>(L, k, nk, bk, vmax, wx, wy, &pa)) {
+        if (lp2_plane(L, k, nk, bk, vmax, wx, wy, &pa)) {
             vx = wx;
             vy = wy;
             t = fmax(bk - (nk.x * vx + nk.y * vy), 0.0);
-            if (REC) {
-                *plane = k;
-                *act = pa;
-            }
+            *plane = k;
+            *act = pa;
         }
     }
     return t;
+}
+
+// Up to three rows taken ahead of the others: copies of rows of the store,
+// with their positions in it (pos < 0: the slot is empty).
+struct FrontRows {
+    double2 n[3];
+    double b[3];
+    int pos[3];
+};
+
+// lp2_project with the front rows taken first and then the other rows of the
+// store in order: the point of the disc and of the half-planes
+// n_k.v >= b_k - relax closest to vhat, from the radial clip of vhat.  Returns -1 (v set) or the position of
+// the first row whose 1D program is empty.  The Active names rows by their
+// position in the store.
+template <int KB, class RS>
+ORCA_HDI inline int lp2_project_front(const RS &L, int m, const FrontRows &F, double relax,
+                                     double vmax, double vhx, double vhy, double &vx, double &vy,
+                                     Active *act)
+{
+    const double vm2 = vmax * vmax;
+    act->line = kLineNone;
+    act->src = kSrcFree;
+    int fail = -1;
+    disc_clip(vmax, vhx, vhy, vx, vy);
+    // one step of the incremental projection on row (nk, bk), given the rows
+    // before it: the filled front slots below nf and store rows 0..nrows-1
+    auto line_step = [&](double2 nk, double bk, int pos, int nf,
+                         int nrows) __attribute__((always_inline)) {
+        ORCA_COUNT(lp2_check);
+        if (nk.x * vx + nk.y * vy >= bk) return;
+        ORCA_COUNT(lp2_line);
+        double h2 = vm2 - bk * bk;
+        if (h2 < 0.0) {
+            if (bk > 0.0) {
+                fail = pos;  // the line misses the disc on the far side
+                return;
+            }
+            h2 = 0.0;
+        }
+        Interval iv;
+        iv.init(sqrt(h2), 1.0);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            if (u < nf && F.pos[u] >= 0) {
+                const double2 nj = F.n[u];
+                ORCA_COUNT(lp2_inner);
+                iv.add(nj.y * nk.x - nj.x * nk.y,
+                       (F.b[u] - relax) - bk * (nj.x * nk.x + nj.y * nk.y), F.pos[u]);
+            }
+        }
+        for (int j = 0; j < nrows; ++j) {
+            const double2 nj = L.N(j);
+            ORCA_COUNT(lp2_inner);
+            iv.add(nj.y * nk.x - nj.x * nk.y, (L.B(j) - relax) - bk * (nj.x * nk.x + nj.y * nk.y),
+                   j);
+        }
+        if (iv.empty()) {
+            fail = pos;
+            return;
+        }
+        double tn, td;
+        const int src = iv.clamp(nk.x * vhy - nk.y * vhx, 1.0, tn, td);  // d_k . vhat, clamped
+        const double t = tn / td;
+        vx = bk * nk.x - t * nk.y;
+        vy = bk * nk.y + t * nk.x;
+        act->line = pos;
+        act->src = src;
+    };
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+        if (F.pos[u] >= 0 && fail < 0) line_step(F.n[u], F.b[u] - relax, F.pos[u], u, 0);
+    for (int k = 0; k < KB; ++k) {
+        // a front row is not taken again: on its own line it would meet itself
+        // as a constraint, with a cross term that rounding leaves nonzero
+        if (k >= m || fail >= 0 || k == F.pos[0] || k == F.pos[1] || k == F.pos[2]) continue;
+        line_step(L.N(k), L.B(k) - relax, k, 3, k);
+    }
+    return fail;
 }
 
 }  // namespace orca

@@ -19,6 +19,10 @@ workloads below follow that recipe at the sizes the measurements use:
   per-scene density, max speed and time horizon.
 * ``grad``          4,096 agents uniform at 1 agent/m^2 with a fixed preferred
   velocity per agent and a target point per agent.
+* ``crossing_hetero`` the two-way crossing whose people differ in size and
+  speed (section 4): two groups swap places; per-agent radius 0.5, 0.75 or
+  1 m and desired speed 1, 1.33 or 2 m/s, each equally likely, max speed 125%
+  of the desired speed.
 
 Every generator is deterministic in its seed (``numpy.random.default_rng``).
 """
@@ -64,6 +68,10 @@ class Workload:
     params: List[SceneParams]
     steps: int
     targets: Optional[np.ndarray] = None
+    # optional per-agent properties [N] float32 (None: the scene's value)
+    radius: Optional[np.ndarray] = None
+    max_speed: Optional[np.ndarray] = None
+    pref_speed: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
@@ -82,9 +90,12 @@ class Workload:
         sizes = [hi - lo for lo, hi in parts]
         offs = np.zeros(len(idx) + 1, np.int64)
         offs[1:] = np.cumsum(sizes)
+        cat1 = lambda a: None if a is None else np.ascontiguousarray(
+            np.concatenate([a[lo:hi] for lo, hi in parts]))
         return Workload(self.name + "_subset", cat(self.pos), cat(self.vel), cat(self.goals),
                         cat(self.pref_vel), offs, [self.params[s] for s in idx], self.steps,
-                        cat(self.targets))
+                        cat(self.targets), cat1(self.radius), cat1(self.max_speed),
+                        cat1(self.pref_speed))
 
 
 def _rsa_square(rng: np.random.Generator, n: int, side: float, dmin: float,
@@ -118,6 +129,58 @@ def _rsa_square(rng: np.random.Generator, n: int, side: float, dmin: float,
                 cand = cand[~drop]
         kept = np.concatenate([kept, cand[: n - kept.shape[0]]], axis=0)
     return kept
+
+
+def _rsa_box_radii(rng: np.random.Generator, radii: np.ndarray, box, margin: float = 1e-4):
+    """Random sequential addition of discs in the box (x0, x1, y0, y1): a
+    proposal of radius r is kept if it is at least r + r_j + margin from every
+    kept disc j and from every earlier proposal of its batch.  Each proposal
+    takes a radius from those not yet placed; returns (centres [n, 2], radii in
+    the order placed), a permutation of ``radii``."""
+    from scipy.spatial import cKDTree
+
+    x0, x1, y0, y1 = box
+    rmax = float(radii.max()) if len(radii) else 0.0
+    reach = 2 * rmax + margin
+    kept = np.empty((0, 2))
+    kept_r = np.empty(0)
+    todo = np.array(radii, dtype=np.float64)
+    tries = 0
+    while todo.size:
+        tries += 1
+        if tries > 10000:
+            raise RuntimeError("random sequential addition did not converge")
+        b = max(256, 2 * todo.size)
+        cand = np.stack([rng.uniform(x0, x1, b), rng.uniform(y0, y1, b)], axis=1)
+        cr = todo[rng.integers(0, todo.size, b)]
+        ok = np.ones(b, bool)
+        if kept.shape[0]:
+            k = min(32, kept.shape[0])
+            d, j = cKDTree(kept).query(cand, k=k, distance_upper_bound=reach)
+            d = d.reshape(b, k)
+            j = j.reshape(b, k)
+            rj = np.where(j < kept.shape[0], kept_r[np.minimum(j, kept.shape[0] - 1)], 0.0)
+            ok = np.all(d >= cr[:, None] + rj + margin, axis=1)
+        pairs = cKDTree(cand).query_pairs(reach, output_type="ndarray")
+        if pairs.size:
+            dd = np.hypot(*(cand[pairs[:, 0]] - cand[pairs[:, 1]]).T)
+            bad = pairs[dd < cr[pairs[:, 0]] + cr[pairs[:, 1]] + margin]
+            ok[bad.max(axis=1)] = False
+        cand, cr = cand[ok], cr[ok]
+        # take only radii still to place (a radius value is used as often as it occurs)
+        vals, counts = np.unique(todo, return_counts=True)
+        take = np.zeros(cand.shape[0], bool)
+        for v, c in zip(vals, counts):
+            idx = np.flatnonzero(cr == v)[:c]
+            take[idx] = True
+        cand, cr = cand[take], cr[take]
+        kept = np.concatenate([kept, cand], axis=0)
+        kept_r = np.concatenate([kept_r, cr])
+        for v in np.unique(cr):
+            c = int(np.sum(cr == v))
+            idx = np.flatnonzero(todo == v)[:c]
+            todo = np.delete(todo, idx)
+    return kept, kept_r
 
 
 def _check_separation(p32: np.ndarray, dmin: float) -> None:
@@ -213,6 +276,38 @@ def grad(n: int = 4096, density: float = 1.0, seed: int = BASE_SEED + 4, steps: 
     return _pack("grad", [pos], None, [p], steps, pref_list=[pref], targets=targets)
 
 
+def crossing_hetero(n: int = 2500, density: float = 0.2, gap: float = 10.0, height: float = 100.0,
+                    seed: int = BASE_SEED + 5, steps: int = 600, **over) -> Workload:
+    """Two-way crossing of people of different sizes and speeds (section 4).
+
+    Two groups of n/2 swap places: each starts in a rectangle of height
+    ``height`` at density ``density`` on one side of a ``2 gap`` wide corridor
+    and heads for its mirror image in the other group's start region.  Radius
+    and desired speed are drawn independently with equal probability from the
+    values the paper gives; max speed is 125% of the desired speed.
+    Positions are random sequential additions with separation r_i + r_j.
+    """
+    rng = np.random.default_rng(seed)
+    kw = {**DEFAULT_PARAMS, "radius": 0.75, "max_speed": 1.25 * 1.33, "pref_speed": 1.33}
+    kw.update(over)
+    p = SceneParams(**kw)
+    half = n // 2
+    width = (half / density) / height
+    radius = rng.choice(np.array([0.5, 0.75, 1.0]), n)
+    speed = rng.choice(np.array([1.0, 1.33, 2.0]), n)
+    left, rl = _rsa_box_radii(rng, radius[:half], (-gap - width, -gap, -height / 2, height / 2))
+    right, rr = _rsa_box_radii(rng, radius[half:], (gap, gap + width, -height / 2, height / 2))
+    radius = np.concatenate([rl, rr])
+    pos = np.concatenate([left, right], axis=0).T
+    goals = pos.copy()
+    goals[0] = -goals[0]
+    w = _pack("crossing_hetero", [pos], [goals], [p], steps)
+    w.radius = radius.astype(np.float32)
+    w.pref_speed = speed.astype(np.float32)
+    w.max_speed = (1.25 * speed).astype(np.float32)
+    return w
+
+
 def tiny_random(n: int, side: float, seed: int, vel_scale: float = 1.0, **over) -> Workload:
     """Small uniform scene with random current and preferred velocities (parity cases)."""
     rng = np.random.default_rng(seed)
@@ -231,4 +326,5 @@ WORKLOADS = {
     "dense_uniform": dense_uniform,
     "batched": batched,
     "grad": grad,
+    "crossing_hetero": crossing_hetero,
 }
