@@ -207,6 +207,31 @@ def adjoint_forms():
     return out
 
 
+def hetero_forms(steps: int, launch):
+    """The two-way crossing whose people differ in size and speed (section 4),
+    262,144 agents: plain steps with per-agent radius, max speed and walking
+    speed."""
+    import torch
+    from paper_1908_10107_amd import orca, scenes
+    w = scenes.crossing_hetero(n=1 << 18)
+    d = orca.to_device(w)
+    ctx = orca.Context(max_agents=w.n, max_scenes=1, k_max=w.params[0].max_neighbors)
+    ctx.set_agents(d["radius"], d["max_speed"], d["pref_speed"])
+    if launch:
+        ctx.set_launch(*launch)
+    step = lambda k: ctx.step(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"],
+                              goals=d["goals"], n_steps=k)
+    step(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return {"hetero_crossing_262k": {"value": w.n * steps / dt, "ms_per_step": 1e3 * dt / steps,
+                                     "agents": w.n, "steps": steps}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,9 +242,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="the CPU reference steps the workload until this much time has passed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,batched,adjoint",
+    ap.add_argument("--forms", default="plain,batched,adjoint,hetero",
                     help="comma list: plain (always), batched (512 scenes, graph replay vs "
-                         "per-scene plain steps), adjoint (forward + adjoint)")
+                         "per-scene plain steps), adjoint (forward + adjoint), hetero "
+                         "(people of different sizes and speeds)")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None,
@@ -312,6 +338,8 @@ def main():
         forms.update(batched_forms(args.batched_steps, args.no_autotune))
     if "adjoint" in args.forms.split(","):
         forms.update(adjoint_forms())
+    if "hetero" in args.forms.split(","):
+        forms.update(hetero_forms(50, tuned if args.launch else None))
 
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

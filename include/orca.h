@@ -179,6 +179,22 @@ int orca_autotune(orca_ctx *ctx, const float *pos, const float *vel, const float
                   const float *goals, float *new_vel, int32_t reps, int32_t *choice);
 
 /*
+ * Optional per-agent properties (section 4: people of different sizes and
+ * speeds): device float32 arrays of at least N entries in agent order, each
+ * nullable (NULL: the scene's radius / max_speed / pref_speed).  A pair's
+ * combined radius is r_i + r_j; max_speed caps the agent's own velocity;
+ * pref_speed is its walking speed toward its goal.  The context keeps the
+ * pointers (the caller keeps the arrays alive and unchanged) and applies them
+ * to every later orca_build_grid, orca_compute_velocities, orca_step and
+ * orca_step_graph until set again; orca_compute_velocities returns ESTATE if
+ * the radii changed since orca_build_grid.  orca_backward uses the radii and
+ * max speeds of the recorded steps; an agent with its own max speed adds
+ * nothing to its scene's max_speed gradient.  Errors: EINVAL (ctx NULL).
+ */
+int orca_set_agents(orca_ctx *ctx, const float *radius, const float *max_speed,
+                    const float *pref_speed);
+
+/*
  * Set the launch shapes directly (the two values orca_autotune picks):
  * knn_block in {64, 128, 256, 512} threads per neighbour block and
  * fb_waves_per_cu in 1..64 persistent fallback waves per compute unit.

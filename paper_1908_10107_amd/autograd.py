@@ -26,12 +26,15 @@ class TrajectorySpec:
     n_steps: int
     segment: int = 20
     ctx: Optional[_orca.Context] = None
+    radius: Optional[torch.Tensor] = None      # per-agent radii [N] (constants), or None
+    max_speed: Optional[torch.Tensor] = None   # per-agent max speeds [N] (constants), or None
 
     def context(self, n):
         if self.ctx is None:
             k = max(1, max(p.max_neighbors for p in self.params))
             self.ctx = _orca.Context(max_agents=n, max_scenes=len(self.params), k_max=k,
                                      tape_steps=self.segment)
+        self.ctx.set_agents(self.radius, self.max_speed)
         return self.ctx
 
 
@@ -68,7 +71,7 @@ class OrcaTrajectory(torch.autograd.Function):
     def backward(ctx, g_pos, g_vel):
         (pref_c,) = ctx.saved_tensors
         spec, params = ctx.spec, ctx.params
-        lib = spec.ctx
+        lib = spec.context(pref_c.shape[1])
         n_sc = len(params)
         gp = (torch.zeros_like(pref_c) if g_pos is None else g_pos).contiguous().clone()
         gv = (torch.zeros_like(pref_c) if g_vel is None else g_vel).contiguous().clone()

@@ -37,8 +37,9 @@ __global__ __launch_bounds__(256) void k_backward(BackArgs a)
         const SceneDev p = a.sp[sc];
         const TapeCode tc = a.codes[i];
         const float4 me = a.state[i];
-        const double R = 2.0 * (double)p.radius, tau = (double)p.tau, dt = (double)p.dt;
-        const double vmax = (double)p.vmax;
+        const double tau = (double)p.tau, dt = (double)p.dt;
+        const double ri = (double)(a.radius ? a.radius[i] : p.radius);
+        const double vmax = (double)(a.max_speed ? a.max_speed[i] : p.vmax);
         const double vix = (double)me.z, viy = (double)me.w;
         const double vhx = (double)a.pref[i], vhy = (double)a.pref[n + i];
         const double gx = (double)a.g_vel_next[i] + dt * (double)a.g_pos_next[i];
@@ -46,11 +47,13 @@ __global__ __launch_bounds__(256) void k_backward(BackArgs a)
         int r[kSlots];
         slot_rows(tc, r);
         RowGeom rows[kSlots];
+        double Rq[kSlots];
         int32_t js[kSlots];
 #pragma unroll
         for (int q = 0; q < kSlots; ++q) {
             js[q] = -1;
             rows[q] = RowGeom{};
+            Rq[q] = 0.0;
             if (r[q] >= 0) {
                 const int32_t j = a.nbr[(int64_t)i * a.krow + r[q]];
                 const float4 o = a.state[j];
@@ -59,7 +62,8 @@ __global__ __launch_bounds__(256) void k_backward(BackArgs a)
                 rows[q].Vx = vix - (double)o.z;
                 rows[q].Vy = viy - (double)o.w;
                 rows[q].first = i < j;
-                row_geom(rows[q], R, tau, dt, vix, viy);
+                Rq[q] = ri + (double)(a.radius ? a.radius[j] : p.radius);
+                row_geom(rows[q], Rq[q], tau, dt, vix, viy);
                 js[q] = j;
             }
         }
@@ -72,8 +76,8 @@ __global__ __launch_bounds__(256) void k_backward(BackArgs a)
         for (int q = 0; q < kSlots; ++q) {
             if (js[q] < 0) continue;
             double gPx = 0.0, gPy = 0.0, gVx = 0.0, gVy = 0.0;
-            row_vjp(rows[q], R, tau, dt, vix, viy, sg.gnx[q], sg.gny[q], sg.gb[q], gPx, gPy, gVx,
-                    gVy, gtau, gvix, gviy);
+            row_vjp(rows[q], Rq[q], tau, dt, vix, viy, sg.gnx[q], sg.gny[q], sg.gb[q], gPx, gPy,
+                    gVx, gVy, gtau, gvix, gviy);
             const int32_t j = js[q];
             // P = x_j - x_i, V = v_i - v_j
             atomicAdd(&a.acc[j], gPx);
@@ -89,6 +93,7 @@ __global__ __launch_bounds__(256) void k_backward(BackArgs a)
         atomicAdd(&a.acc[3 * n + i], gviy);
         a.g_pref[i] += (float)gvhx;
         a.g_pref[n + i] += (float)gvhy;
+        if (a.max_speed) gvmax = 0.0;  // the agent's own max speed is a constant here
     }
     // per-scene parameters: one atomic per wave when the wave is one scene
     const int32_t sc0 = __shfl(sc, 0, 64);

@@ -46,7 +46,11 @@ struct orca_ctx {
     int32_t *fb_order = nullptr;
     double2 *stash_n = nullptr;
     double *stash_b = nullptr;
+    float *srad = nullptr;  // per-agent radii in cell order
     std::vector<void *> allocs;
+
+    // optional per-agent properties (caller's device arrays), see orca_set_agents
+    const float *a_radius = nullptr, *a_vmax = nullptr, *a_speed = nullptr;
 
     // scene set currently on the device
     int32_t n_scenes = 0;
@@ -62,6 +66,7 @@ struct orca_ctx {
     // grid state
     bool grid_valid = false;
     const float *grid_pos = nullptr;
+    const float *grid_radius = nullptr;  // per-agent radii the grid's sorted copy came from
 
     // per-stage timing (diagnostics): events on the context stream between stages
     bool profiling = false;
@@ -78,6 +83,7 @@ struct orca_ctx {
     int32_t tape_len = 0;                   // steps held by the last recording
     uint64_t tape_scene_version = 0;
     const float *tape_pref = nullptr;
+    const float *tape_radius = nullptr, *tape_vmax = nullptr;
 
     // launch shapes (orca_autotune picks them)
     int32_t knn_block = 256, fb_waves_per_cu = 16;
@@ -86,7 +92,7 @@ struct orca_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    const void *graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
+    const void *graph_key[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     uint64_t graph_scene_version = 0, scene_version = 0;
     int32_t graph_knn_block = 0, graph_fb = 0;
 
@@ -244,6 +250,10 @@ orca::Plan make_plan(const orca_ctx *ctx)
     p.fb_order = ctx->fb_order;
     p.stash_n = ctx->stash_n;
     p.stash_b = ctx->stash_b;
+    p.out.ag.radius = ctx->a_radius;
+    p.out.ag.max_speed = ctx->a_vmax;
+    p.out.ag.pref_speed = ctx->a_speed;
+    p.out.ag.srad = ctx->srad;
     return p;
 }
 
@@ -376,6 +386,7 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->fb_order, sizeof(int32_t) * A) &&
               alloc((void **)&ctx->stash_n, sizeof(double2) * A * (size_t)k_max) &&
               alloc((void **)&ctx->stash_b, sizeof(double) * A * (size_t)k_max) &&
+              alloc((void **)&ctx->srad, sizeof(float) * A) &&
               alloc((void **)&ctx->acc, sizeof(double) * 4 * A) &&
               alloc((void **)&ctx->acc_scene, sizeof(double) * 2 * S);
     const size_t T = (size_t)tape_steps;
@@ -431,6 +442,17 @@ int orca_build_grid(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
     HIP_OK(orca::launch_grid(pl, pos, nullptr, ctx->stream));
     ctx->grid_valid = true;
     ctx->grid_pos = pos;
+    ctx->grid_radius = ctx->a_radius;
+    return ORCA_OK;
+}
+
+int orca_set_agents(orca_ctx *ctx, const float *radius, const float *max_speed,
+                    const float *pref_speed)
+{
+    if (!ctx) return ORCA_EINVAL;
+    ctx->a_radius = radius;
+    ctx->a_vmax = max_speed;
+    ctx->a_speed = pref_speed;
     return ORCA_OK;
 }
 
@@ -441,6 +463,8 @@ int orca_compute_velocities(orca_ctx *ctx, const float *pos, const float *vel,
     if (!ctx) return ORCA_EINVAL;
     if (!ctx->grid_valid || pos != ctx->grid_pos)
         return fail(ctx, ORCA_ESTATE, "orca_build_grid must be called first on the same pos");
+    if (ctx->grid_radius != ctx->a_radius)
+        return fail(ctx, ORCA_ESTATE, "per-agent radii changed since orca_build_grid");
     if (ctx->n > 0 && (!vel || !new_vel || (!goals && !pref_vel)))
         return fail(ctx, ORCA_EINVAL, "vel, new_vel and pref_vel (or goals) must be non-NULL");
     orca::Plan pl = make_plan(ctx);
@@ -493,6 +517,8 @@ int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
         ctx->tape_len = n_steps;
         ctx->tape_scene_version = ctx->scene_version;
         ctx->tape_pref = pref_vel;
+        ctx->tape_radius = ctx->a_radius;
+        ctx->tape_vmax = ctx->a_vmax;
     }
     return ORCA_OK;
 }
@@ -509,7 +535,7 @@ int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
     if (ctx->n > 0 && (!pos || !vel || !pref_vel))
         return fail(ctx, ORCA_EINVAL, "pos, vel and pref_vel must be non-NULL");
     ctx->grid_valid = false;
-    const void *key[4] = {pos, vel, pref_vel, goals};
+    const void *key[7] = {pos, vel, pref_vel, goals, ctx->a_radius, ctx->a_vmax, ctx->a_speed};
     const bool fresh = ctx->graph_exec && memcmp(key, ctx->graph_key, sizeof(key)) == 0 &&
                        ctx->graph_scene_version == ctx->scene_version &&
                        ctx->graph_knn_block == ctx->knn_block &&
@@ -661,6 +687,8 @@ int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
     a.g_time_horizon = g_time_horizon;
     a.acc = ctx->acc;
     a.acc_scene = ctx->acc_scene;
+    a.radius = ctx->tape_radius;
+    a.max_speed = ctx->tape_vmax;
     HIP_OK(orca::launch_backward(a, ctx->stream));
     return ORCA_OK;
 }

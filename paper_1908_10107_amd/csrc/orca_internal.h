@@ -88,6 +88,15 @@ __host__ __device__ __forceinline__ int stash_row(int p, const FallbackItem &it)
     return k >= worst ? k + 1 : k;
 }
 
+// Optional per-agent properties, indexed by agent (nullptr: the scene's
+// value).  srad holds the radii in cell order when radius is given.
+struct AgentProps {
+    const float *radius;
+    const float *max_speed;
+    const float *pref_speed;
+    float *srad;
+};
+
 // Where the velocity kernels put their results.  Step mode has pos != nullptr.
 struct OutArgs {
     float *new_vel;      // [2, N] or nullptr
@@ -100,6 +109,7 @@ struct OutArgs {
     int32_t krow;
     float4 *tape_state;  // recorded step: state (x, y, vx, vy) at the step's start, or nullptr
     TapeCode *tape_codes;  // recorded step: how each velocity was chosen
+    AgentProps ag;         // per-agent properties of this pass
 };
 
 // Device buffers and sizes of one launch sequence.
@@ -148,6 +158,8 @@ struct BackArgs {
     const float *pref;        // fixed preferred velocities [2, n]
     const float *g_pos_next, *g_vel_next;
     float *g_pos, *g_vel, *g_pref, *g_max_speed, *g_time_horizon;
+    const float *radius;      // per-agent radii of the recorded step, or nullptr
+    const float *max_speed;   // per-agent max speeds of the recorded step, or nullptr
     double *acc;              // [4, n] float64 accumulators (kept zero between uses)
     double *acc_scene;        // [2, n_scenes]
 };

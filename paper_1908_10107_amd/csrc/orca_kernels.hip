@@ -335,12 +335,15 @@ __global__ __launch_bounds__(256) void k_scatter(const float *__restrict__ pos,
                                                  float4 *__restrict__ sorted,
                                                  int32_t *__restrict__ sid,
                                                  int32_t *__restrict__ skey,
-                                                 int32_t *__restrict__ inv)
+                                                 int32_t *__restrict__ inv,
+                                                 const float *__restrict__ radius,
+                                                 float *__restrict__ srad)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t k = key[i];
     const int32_t d = cell_start[k] + rank[i];
+    if (radius) srad[d] = radius[i];
     float4 r;
     r.x = pos[i];
     r.y = pos[n + i];
@@ -500,7 +503,8 @@ struct LpRows<KMAX, false> {
 // only when they are written out (the pair order comes with the entry).
 template <int KMAX, class Rows>
 __device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t id, float4 me,
-                                                 const SceneDev &p, const float4 *__restrict__ sorted,
+                                                 const SceneDev &p, const AgentProps &ag,
+                                                 const float4 *__restrict__ sorted,
                                                  const int32_t *__restrict__ sid,
                                                  const int32_t *__restrict__ nbr, int32_t ld,
                                                  const int32_t *__restrict__ ncount,
@@ -508,13 +512,15 @@ __device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t 
 {
     constexpr int G = 8;
     const int32_t m = ncount[s];
-    const double R = 2.0 * (double)p.radius;
+    // combined radius r_i + r_j (section 4: people of different sizes)
+    const double ri = (double)(ag.radius ? ag.radius[id] : p.radius);
     const double tau = (double)p.tau, dt = (double)p.dt;
     const double vix = (double)me.z, viy = (double)me.w;
 #pragma unroll
     for (int k0 = 0; k0 < KMAX; k0 += G) {
         int32_t e[G];
         float4 o[G];
+        float rj[G];
 #pragma unroll
         for (int u = 0; u < G; ++u)
             e[u] = k0 + u < KMAX && k0 + u < m ? nbr[(int64_t)(k0 + u) * ld + s] : 0;
@@ -522,6 +528,9 @@ __device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t 
         for (int u = 0; u < G; ++u)
             o[u] = k0 + u < KMAX && k0 + u < m ? sorted[e[u] & 0x7fffffff]
                                                : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+            rj[u] = ag.radius && k0 + u < KMAX && k0 + u < m ? ag.srad[e[u] & 0x7fffffff] : p.radius;
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int k = k0 + u;
@@ -532,7 +541,7 @@ __device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t 
                 const double Px = (double)o[u].x - (double)me.x, Py = (double)o[u].y - (double)me.y;
                 const double Vx = vix - (double)o[u].z, Vy = viy - (double)o[u].w;
                 double ux, uy, nx, ny;
-                obstacle_exit(Px, Py, Vx, Vy, R, tau, dt, e[u] >= 0, ux, uy, nx, ny);
+                obstacle_exit(Px, Py, Vx, Vy, ri + (double)rj[u], tau, dt, e[u] >= 0, ux, uy, nx, ny);
                 const double qx = vix + 0.5 * ux, qy = viy + 0.5 * uy;
                 nk = make_double2(nx, ny);
                 bk = nx * qx + ny * qy;
@@ -545,8 +554,9 @@ __device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t 
     return m;
 }
 
-__device__ __forceinline__ void preferred_velocity(const SceneDev &p, float4 me, int32_t id,
-                                                   int32_t n, const float *__restrict__ pref,
+__device__ __forceinline__ void preferred_velocity(const SceneDev &p, const AgentProps &ag,
+                                                   float4 me, int32_t id, int32_t n,
+                                                   const float *__restrict__ pref,
                                                    const float *__restrict__ goals, double &vhx,
                                                    double &vhy)
 {
@@ -556,7 +566,8 @@ __device__ __forceinline__ void preferred_velocity(const SceneDev &p, float4 me,
         const double ex = (double)goals[id] - (double)me.x;
         const double ey = (double)goals[n + id] - (double)me.y;
         const double el = sqrt(ex * ex + ey * ey);
-        const double s = (double)p.pref_speed, dt = (double)p.dt;
+        const double s = (double)(ag.pref_speed ? ag.pref_speed[id] : p.pref_speed);
+        const double dt = (double)p.dt;
         if (el > s * dt) {
             vhx = s * ex / el;
             vhy = s * ey / el;
@@ -624,12 +635,13 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
         const int32_t id = sid[s];
         const SceneDev p = sp[agent_scene[id]];
         double vhx, vhy;
-        preferred_velocity(p, me, id, n, out.pref, out.goals, vhx, vhy);
-        const double vmax = (double)p.vmax;
+        preferred_velocity(p, out.ag, me, id, n, out.pref, out.goals, vhx, vhy);
+        const float vmaxf = out.ag.max_speed ? out.ag.max_speed[id] : p.vmax;
+        const double vmax = (double)vmaxf;
         double vx, vy;
         disc_clip(vmax, vhx, vhy, vx, vy);
-        const int m = build_constraints<KMAX>(rows, s, id, me, p, sorted, sid, nbr, ld, ncount,
-                                              out.nbr_out, out.krow);
+        const int m = build_constraints<KMAX>(rows, s, id, me, p, out.ag, sorted, sid, nbr, ld,
+                                              ncount, out.nbr_out, out.krow);
         Active act;
         const int fail = rows.project(m, vmax, vhx, vhy, vx, vy, &act);
         if (REC) out.tape_state[id] = me;
@@ -672,7 +684,7 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
             it.vy = vy;
             it.vhx = vhx;
             it.vhy = vhy;
-            it.vmax = p.vmax;
+            it.vmax = vmaxf;
             it.dt = p.dt;
             it.mex = me.x;
             it.mey = me.y;
@@ -978,7 +990,8 @@ hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, hipSt
     hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kScanBlock), 0, st, pl.counts,
                        pl.counters, pl.partial, pl.cell_start, n);
     hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, st, pos, vel, n, pl.key,
-                       pl.rank, pl.cell_start, pl.sorted, pl.sid, pl.skey, pl.inv);
+                       pl.rank, pl.cell_start, pl.sorted, pl.sid, pl.skey, pl.inv,
+                       pl.out.ag.radius, pl.out.ag.srad);
     return hipGetLastError();
 }
 

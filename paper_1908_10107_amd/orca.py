@@ -82,6 +82,8 @@ def load(path: str = LIB_PATH):
     L.orca_autotune.restype = ctypes.c_int
     L.orca_set_launch.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
     L.orca_set_launch.restype = ctypes.c_int
+    L.orca_set_agents.argtypes = [_P, _P, _P, _P]
+    L.orca_set_agents.restype = ctypes.c_int
     L.orca_profile.argtypes = [_P, ctypes.c_int32]
     L.orca_profile.restype = ctypes.c_int
     L.orca_profile_read.argtypes = [_P, _P, _P, _P]
@@ -208,6 +210,23 @@ class Context:
                                            int(reps), choice))
         return choice[0], choice[1]
 
+    def set_agents(self, radius=None, max_speed=None, pref_speed=None):
+        """Per-agent radius / max speed / walking speed ([N] float32 CUDA tensors, each
+        optional) for the following calls (see orca_set_agents).  The tensors are
+        kept referenced here; pass nothing to return to the scene values."""
+        ptrs = []
+        for t, nm in ((radius, "radius"), (max_speed, "max_speed"), (pref_speed, "pref_speed")):
+            if t is None:
+                ptrs.append(None)
+                continue
+            if not (t.is_cuda and t.dtype == self._torch.float32 and t.dim() == 1 and
+                    t.is_contiguous()):
+                raise TypeError("%s must be a contiguous 1-D float32 CUDA tensor" % nm)
+            ptrs.append(ctypes.c_void_p(t.data_ptr()))
+        self._sync_stream()
+        self._check(self.lib.orca_set_agents(self.h, *ptrs))
+        self._agents = (radius, max_speed, pref_speed)
+
     def set_launch(self, knn_block, fallback_waves_per_cu):
         """Fix the launch shapes that autotune would pick (see orca_set_launch)."""
         self._check(self.lib.orca_set_launch(self.h, int(knn_block), int(fallback_waves_per_cu)))
@@ -264,4 +283,6 @@ def to_device(w, device="cuda"):
     """Copy a scenes.Workload's arrays into float32 GPU tensors (dict)."""
     import torch
     t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)
-    return dict(pos=t(w.pos), vel=t(w.vel), pref_vel=t(w.pref_vel), goals=t(w.goals))
+    return dict(pos=t(w.pos), vel=t(w.vel), pref_vel=t(w.pref_vel), goals=t(w.goals),
+                radius=t(getattr(w, "radius", None)), max_speed=t(getattr(w, "max_speed", None)),
+                pref_speed=t(getattr(w, "pref_speed", None)))

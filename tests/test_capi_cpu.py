@@ -52,6 +52,7 @@ def test_null_context_calls(lib):
     assert lib.orca_backward(None, 0, *([None] * 7)) == orca.EINVAL
     assert lib.orca_set_stream(None, None) == orca.EINVAL
     assert lib.orca_set_launch(None, 256, 16) == orca.EINVAL
+    assert lib.orca_set_agents(None, None, None, None) == orca.EINVAL
     lib.orca_destroy(None)
 
 

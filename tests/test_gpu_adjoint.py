@@ -44,15 +44,21 @@ def moving_scene(n, density, seed, **over):
     return w
 
 
-@pytest.mark.parametrize("case", ["moderate", "dense"])
+@pytest.mark.parametrize("case", ["moderate", "dense", "hetero"])
 def test_step_vjp_dot_product(case):
     torch = _torch()
     from paper_1908_10107_amd import orca
     say("case step vjp", case)
-    w = moving_scene(3000, 1.0, 41) if case == "moderate" else moving_scene(3000, 2.5, 42)
+    w = moving_scene(3000, 2.5, 42) if case == "dense" else moving_scene(3000, 1.0, 41)
+    if case == "hetero":
+        # per-agent radii and max speeds (section 4), constants of the step
+        rng = np.random.default_rng(43)
+        w.radius = rng.choice(np.array([0.1, 0.25, 0.5], np.float32), w.n)
+        w.max_speed = rng.uniform(0.8, 2.0, w.n).astype(np.float32)
     d = orca.to_device(w)
     k = w.params[0].max_neighbors
     ctx = orca.Context(max_agents=w.n, max_scenes=1, k_max=k, tape_steps=1)
+    ctx.set_agents(d["radius"], d["max_speed"])
     p1, v1 = d["pos"].clone(), d["vel"].clone()
     ctx.step(w.offsets, w.params, p1, v1, d["pref_vel"], n_steps=1, save_tape=True)
     p2, v2 = d["pos"].clone(), d["vel"].clone()
@@ -76,7 +82,7 @@ def test_step_vjp_dot_product(case):
             dpos[:] = 0.0
             dvel[:] = 0.0   # parameters only
         jp, jv = oracle.step_jvp(w.pos, w.vel, w.pref_vel, w.offsets, w.params, dpos, dvel,
-                                 dpref, dvm, dta)
+                                 dpref, dvm, dta, radius=w.radius, max_speed=w.max_speed)
         lhs = float((gxn.astype(np.float64) * jp).sum() + (gvn.astype(np.float64) * jv).sum())
         G = lambda a: a.cpu().numpy().astype(np.float64)
         rhs = float((G(gx) * dpos).sum() + (G(gv) * dvel).sum() + (G(gp) * dpref).sum()

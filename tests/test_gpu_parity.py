@@ -34,6 +34,11 @@ def say(*a):
     sys.stdout.flush()
 
 
+def props(w):
+    """Per-agent properties of a workload, as the oracle takes them."""
+    return dict(radius=w.radius, max_speed=w.max_speed, pref_speed=w.pref_speed)
+
+
 def gpu_velocities(w, use_goals=True, ctx=None):
     torch = _torch()
     from paper_1908_10107_amd import orca
@@ -42,6 +47,7 @@ def gpu_velocities(w, use_goals=True, ctx=None):
     if own:
         ctx = orca.Context(max_agents=max(w.n, 1), max_scenes=w.n_scenes, k_max=kmax)
     d = orca.to_device(w)
+    ctx.set_agents(d["radius"], d["max_speed"], d["pref_speed"])
     krow = max(p.max_neighbors for p in w.params)
     nbr = torch.full((max(w.n, 1), max(krow, 1)), -7, dtype=torch.int32, device="cuda")
     st = torch.full((max(w.n, 1),), 9, dtype=torch.uint8, device="cuda")
@@ -99,7 +105,8 @@ def test_velocities_random(n, side, seed, k, vs):
     say("case random n=%d side=%g seed=%d k=%d" % (n, side, seed, k))
     w = scenes.tiny_random(n, side, seed=100 + seed, vel_scale=vs, max_neighbors=k)
     g = gpu_velocities(w, use_goals=False)
-    o = oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params, neighbor_mode=0)
+    o = oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params, neighbor_mode=0,
+                          **props(w))
     compare(w, g, o, label="random n=%d k=%d" % (n, k))
 
 
@@ -122,7 +129,8 @@ def test_coincident_and_head_on():
     w.pos, w.vel = pos, vel
     w.pref_vel = np.ascontiguousarray(vel * 1.1)
     g = gpu_velocities(w, use_goals=False)
-    o = oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params, neighbor_mode=0)
+    o = oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params, neighbor_mode=0,
+                          **props(w))
     compare(w, g, o, label="coincident")
 
 
@@ -144,8 +152,58 @@ def test_knn_exact_ties_and_stacked_agents(k):
     w.vel = np.ascontiguousarray((rng.normal(size=(2, n)) * 0.3).astype(np.float32))
     w.pref_vel = np.ascontiguousarray((rng.normal(size=(2, n)) * 0.8).astype(np.float32))
     g = gpu_velocities(w, use_goals=False)
-    o = oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params, neighbor_mode=0)
+    o = oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params, neighbor_mode=0,
+                          **props(w))
     compare(w, g, o, label="lattice+stack k=%d" % k)
+
+
+def test_hetero_crossing_velocities():
+    """The two-way crossing of people of different sizes and speeds (section 4):
+    per-agent radius, max speed and walking speed."""
+    say("case crossing_hetero 2500")
+    w = scenes.crossing_hetero()
+    g = gpu_velocities(w, use_goals=True)
+    o = oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params, goals=w.goals,
+                          neighbor_mode=0, **props(w))
+    compare(w, g, o, label="crossing_hetero")
+
+
+@pytest.mark.parametrize("which", ["radius", "max_speed", "all"])
+def test_hetero_random(which):
+    """Random overlapping scene with random per-agent properties; max speeds
+    below the walking speed exercise the radial clip."""
+    say("case hetero random", which)
+    w = scenes.tiny_random(2500, 40.0, seed=61, vel_scale=1.0, max_neighbors=16)
+    rng = np.random.default_rng(62)
+    if which in ("radius", "all"):
+        w.radius = rng.choice(np.array([0.1, 0.5, 0.75, 1.0], np.float32), w.n)
+    if which in ("max_speed", "all"):
+        w.max_speed = rng.uniform(0.5, 2.5, w.n).astype(np.float32)
+    if which == "all":
+        w.pref_speed = rng.uniform(0.8, 2.0, w.n).astype(np.float32)
+    g = gpu_velocities(w, use_goals=which == "all")
+    o = oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params,
+                          goals=w.goals if which == "all" else None, neighbor_mode=0, **props(w))
+    compare(w, g, o, label="hetero %s" % which)
+
+
+def test_hetero_crossing_steps():
+    """60 steps of the heterogeneous crossing, each checked from the GPU's state."""
+    say("case crossing_hetero steps")
+    step_parity(scenes.crossing_hetero(), 60, label="crossing_hetero", every=6)
+
+
+def test_agent_radii_must_match_the_grid():
+    torch = _torch()
+    from paper_1908_10107_amd import orca
+    w = scenes.crossing_hetero(n=200)
+    d = orca.to_device(w)
+    ctx = orca.Context(max_agents=w.n, max_scenes=1, k_max=10)
+    ctx.build_grid(w.offsets, w.params, d["pos"])
+    ctx.set_agents(d["radius"])
+    with pytest.raises(orca.OrcaError):
+        ctx.compute_velocities(d["pos"], d["vel"], goals=d["goals"])
+    ctx.close()
 
 
 def test_multi_scene_with_empty_scenes():
@@ -222,6 +280,7 @@ def step_parity(w, n_steps, sample=None, label="", ctx=None, every=1):
     if own:
         ctx = orca.Context(max_agents=w.n, max_scenes=w.n_scenes, k_max=kmax)
     d = orca.to_device(w)
+    ctx.set_agents(d["radius"], d["max_speed"], d["pref_speed"])
     rng = np.random.default_rng(5)
     dt = np.array([np.float32(p.dt) for p in w.params], np.float64)
     scene = np.repeat(np.arange(w.n_scenes), np.diff(w.offsets))
@@ -238,7 +297,7 @@ def step_parity(w, n_steps, sample=None, label="", ctx=None, every=1):
         torch.cuda.synchronize()
         agents = None if sample is None else np.sort(rng.choice(w.n, sample, replace=False))
         o = oracle.velocities(pos0, vel0, pref0, w.offsets, w.params, goals=w.goals,
-                              agents=agents, neighbor_mode=1)
+                              agents=agents, neighbor_mode=1, **props(w))
         idx = np.arange(w.n) if agents is None else agents
         v1 = d["vel"].cpu().numpy().T[idx].astype(np.float64)
         p1 = d["pos"].cpu().numpy().T[idx].astype(np.float64)
