@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_grid(int32_t n_scenes, const int32_t *_
             const float x1 = float_from_ord(bbox[4 * s + 2]);
             const float y1 = float_from_ord(bbox[4 * s + 3]);
             const double ex = (double)x1 - (double)x0, ey = (double)y1 - (double)y0;
-            g.cell = (double)sp[s].nd * kCellMargin * f;
+            g.cell = (double)sp[s].nd * kCellMargin * f / (double)kCellsPerNd;
             const bool ok = off[s + 1] > off[s] && isfinite(ex) && isfinite(ey) && ex >= 0.0 &&
                             ey >= 0.0 && iter < 23;
             if (ok) {
@@ -405,11 +405,29 @@ __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) best[k] = ~0ull;
     uint64_t worst = ~0ull;  // current K-th entry
-    const int32_t c0 = max(cx - 1, 0), c1 = min(cx + 1, g.nx - 1);
-    // own row first: the list fills with near candidates and prunes the rest
-    for (int32_t r = 0; r < 3; ++r) {
-        const int32_t row = cy + (r == 0 ? 0 : (r == 1 ? -1 : 1));
+    // Cells are about nd/2 wide, so the disc of radius nd reaches two rows and
+    // columns out (one once the grid was widened to nd).  Each row is read over
+    // the cells its chord of the disc touches (one contiguous run of sorted
+    // indices), own row first.  The chord is taken a little wider than nd, so
+    // rounding of the cell arithmetic or of the float32 distance never drops a
+    // neighbour: the distance test below decides.
+    const double cell = g.cell, nd = (double)sp[sc].nd;
+    const int32_t reach = cell >= nd ? 1 : 2;
+    const double px = (double)me.x, py = (double)me.y;
+    const double ndx = nd * (1.0 + 1e-6) + 1e-9 * (1.0 + fabs(px) + fabs(py));
+    for (int32_t q = 0; q <= 2 * reach; ++q) {
+        const int32_t dy = (q & 1) ? -((q + 1) >> 1) : (q >> 1);  // 0, -1, +1, -2, +2
+        const int32_t row = cy + dy;
         if (row < 0 || row >= g.ny) continue;
+        double dyc = 0.0;  // distance from the agent to the row's band in y
+        if (dy > 0) dyc = fmax(g.y0 + (double)row * cell - py, 0.0);
+        if (dy < 0) dyc = fmax(py - (g.y0 + (double)(row + 1) * cell), 0.0);
+        if (dyc >= ndx) continue;
+        const double hw = sqrt(ndx * ndx - dyc * dyc);
+        const int32_t c0 = max((int32_t)fmax(floor((px - hw - g.x0) / cell), -1.0), max(cx - reach, 0));
+        const int32_t c1 = min((int32_t)fmin(floor((px + hw - g.x0) / cell), (double)g.nx),
+                               min(cx + reach, g.nx - 1));
+        if (c0 > c1) continue;
         const int32_t rb = g.base + row * g.nx;
         const int32_t beg = cell_start[rb + c0], end = cell_start[rb + c1 + 1];
         for (int32_t j = beg; j < end; ++j) {
