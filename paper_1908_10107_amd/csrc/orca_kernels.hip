@@ -367,6 +367,29 @@ __global__ __launch_bounds__(256) void k_fill_vel(const float *__restrict__ vel,
 
 // ------------------------------------------------------------------ neighbours
 
+// Offer a (d2 bits << 32 | id) key to the sorted list best[0..K) whose K-th
+// entry is `worst`.
+template <int KMAX>
+__device__ __forceinline__ void knn_offer(uint64_t (&best)[KMAX], uint64_t &worst, int32_t K,
+                                          uint64_t key)
+{
+    if (key >= worst) return;
+#pragma unroll
+    for (int k = KMAX - 1; k > 0; --k) {
+        const bool shift = key < best[k - 1];
+        const bool here = key < best[k];
+        best[k] = shift ? best[k - 1] : (here ? key : best[k]);
+    }
+    best[0] = key < best[0] ? key : best[0];
+    if (K == KMAX) {
+        worst = best[KMAX - 1];
+    } else {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k == K - 1) worst = best[k];
+    }
+}
+
 // K nearest of each agent (sorted order s) among the agents of its 3x3 cells,
 // strictly inside neighbor_dist, nearest first, ties by agent id.  The running
 // list holds (float32 bits of d2) << 32 | id, so one 64-bit compare orders by
@@ -430,28 +453,29 @@ __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
         if (c0 > c1) continue;
         const int32_t rb = g.base + row * g.nx;
         const int32_t beg = cell_start[rb + c0], end = cell_start[rb + c1 + 1];
-        for (int32_t j = beg; j < end; ++j) {
+        // candidates kBatch at a time: their positions and ids are loaded
+        // together, so one memory latency covers the batch
+        constexpr int kBatch = KMAX <= 16 ? 4 : 2;
+        int32_t j = beg;
+        for (; j + kBatch <= end; j += kBatch) {
+            float4 o[kBatch];
+            uint32_t idb[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) o[u] = sorted[j + u];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) idb[u] = (uint32_t)sid[j + u];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const float d2 = dist2_f32(me.x, me.y, o[u].x, o[u].y);
+                if (d2 < nd2 && j + u != s)
+                    knn_offer<KMAX>(best, worst, K, ((uint64_t)__float_as_uint(d2) << 32) | idb[u]);
+            }
+        }
+        for (; j < end; ++j) {
             const float4 o = sorted[j];
             const float d2 = dist2_f32(me.x, me.y, o.x, o.y);
-            if (d2 < nd2 && j != s) {
-                const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)sid[j];
-                if (key < worst) {
-#pragma unroll
-                    for (int k = KMAX - 1; k > 0; --k) {
-                        const bool shift = key < best[k - 1];
-                        const bool here = key < best[k];
-                        best[k] = shift ? best[k - 1] : (here ? key : best[k]);
-                    }
-                    best[0] = key < best[0] ? key : best[0];
-                    if (K == KMAX) {
-                        worst = best[KMAX - 1];
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < KMAX; ++k)
-                            if (k == K - 1) worst = best[k];
-                    }
-                }
-            }
+            if (d2 < nd2 && j != s)
+                knn_offer<KMAX>(best, worst, K, ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)sid[j]);
         }
     }
     int32_t cnt = 0;
