@@ -50,57 +50,48 @@ ORCA_HD inline void obstacle_exit(double Px, double Py, double Vx, double Vy, do
                                               double &uy, double &nx, double &ny)
 {
 #pragma clang fp contract(off)
+    // The cases share their arithmetic in two groups, so a wave whose lanes
+    // fall in different cases runs two paths, not four; each case still does
+    // exactly its own operations in its own order:
+    //   circle: the cut-off arc (apart, look-ahead tau) or, for a pair
+    //           already in contact, the one-step disc (dt in place of tau);
+    //   legs:   the left or right tangent leg, mirror images by a sign.
     const double dist2 = Px * Px + Py * Py;
     const double R2 = R * R;
-    if (dist2 > R2) {
-        const double wx = Vx - Px / tau, wy = Vy - Py / tau;
-        const double w2 = wx * wx + wy * wy;
-        const double wP = wx * Px + wy * Py;
-        if (wP < 0.0 && wP * wP > R2 * w2) {
-            // V faces the cut-off arc
-            const double wl = sqrt(w2);
+    const bool apart = dist2 > R2;
+    const double tc = apart ? tau : dt;
+    const double wx = Vx - Px / tc, wy = Vy - Py / tc;
+    const double w2 = wx * wx + wy * wy;
+    const double wP = wx * Px + wy * Py;
+    if (!apart || (wP < 0.0 && wP * wP > R2 * w2)) {
+        const double wl = sqrt(w2);
+        if (wl > 0.0) {
             nx = wx / wl;
             ny = wy / wl;
-            const double f = R / tau - wl;
-            ux = f * nx;
-            uy = f * ny;
-            return;
-        }
-        // nearest boundary point on a tangent leg; left if V is left of P
-        const double L = sqrt(dist2 - R2);
-        double lx, ly;
-        if (Px * wy - Py * wx > 0.0) {
-            lx = (Px * L - Py * R) / dist2;
-            ly = (Px * R + Py * L) / dist2;
-            nx = -ly;
-            ny = lx;
+        } else if (dist2 > 0.0) {
+            // in contact and not moving apart: away from the neighbour
+            const double pl = sqrt(dist2);
+            nx = -Px / pl;
+            ny = -Py / pl;
         } else {
-            lx = (Px * L + Py * R) / dist2;
-            ly = (-Px * R + Py * L) / dist2;
-            nx = ly;
-            ny = -lx;
+            nx = i_first ? 1.0 : -1.0;
+            ny = 0.0;
         }
-        const double sdot = Vx * lx + Vy * ly;
-        ux = sdot * lx - Vx;
-        uy = sdot * ly - Vy;
+        const double f = R / tc - wl;
+        ux = f * nx;
+        uy = f * ny;
         return;
     }
-    const double wx = Vx - Px / dt, wy = Vy - Py / dt;
-    const double wl = sqrt(wx * wx + wy * wy);
-    if (wl > 0.0) {
-        nx = wx / wl;
-        ny = wy / wl;
-    } else if (dist2 > 0.0) {
-        const double pl = sqrt(dist2);
-        nx = -Px / pl;
-        ny = -Py / pl;
-    } else {
-        nx = i_first ? 1.0 : -1.0;
-        ny = 0.0;
-    }
-    const double f = R / dt - wl;
-    ux = f * nx;
-    uy = f * ny;
+    // nearest boundary point on a tangent leg: left (sg = +1) if w is left of P
+    const double L = sqrt(dist2 - R2);
+    const double sg = Px * wy - Py * wx > 0.0 ? 1.0 : -1.0;
+    const double lx = (Px * L - sg * (Py * R)) / dist2;
+    const double ly = (sg * (Px * R) + Py * L) / dist2;
+    nx = -sg * ly;
+    ny = sg * lx;
+    const double sdot = Vx * lx + Vy * ly;
+    ux = sdot * lx - Vx;
+    uy = sdot * ly - Vy;
 }
 
 // Constraint store of one lane in the block's LDS: half-plane k is
