@@ -45,9 +45,10 @@ class HalfPlane(ctypes.Structure):
 
 
 class OracleAgents(ctypes.Structure):
-    """Per-agent radius, max speed and walking speed ([N] float32 or NULL each)."""
+    """Per-agent radius, max speed and walking speed ([N] float32 or NULL each) and
+    presence ([N] uint8, 0 = not in the simulation, or NULL)."""
     _fields_ = [("radius", ctypes.c_void_p), ("max_speed", ctypes.c_void_p),
-                ("pref_speed", ctypes.c_void_p)]
+                ("pref_speed", ctypes.c_void_p), ("present", ctypes.c_void_p)]
 
 
 _lib = None
@@ -94,9 +95,10 @@ def _f32(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float32)
 
 
-def _agents(radius=None, max_speed=None, pref_speed=None):
+def _agents(radius=None, max_speed=None, pref_speed=None, present=None):
     """(OracleAgents or None, arrays to keep alive) for optional per-agent properties."""
     arrs = [_f32(a) for a in (radius, max_speed, pref_speed)]
+    arrs.append(None if present is None else np.ascontiguousarray(present, np.uint8))
     if all(a is None for a in arrs):
         return None, arrs
     return ctypes.byref(OracleAgents(*[_ptr(a) for a in arrs])), arrs
@@ -195,15 +197,16 @@ def knn_binned(pos, nd, k, lo=0, hi=None):
 # ---------------------------------------------------------------- whole state
 
 def velocities(pos, vel, pref, offsets, params, goals=None, agents=None, neighbor_mode=1,
-               radius=None, max_speed=None, pref_speed=None):
+               radius=None, max_speed=None, pref_speed=None, present=None):
     """New velocities (float64) of ``agents`` (default: all) from one state.
 
     radius, max_speed, pref_speed: optional per-agent values [N] in place of
-    the scene's.  Returns a dict with new_vel [M,2], vhat [M,2], nbr [M,kcap]
-    (-1 padded), n_nbr [M], status [M] (0 = 2D LP, 1 = fallback) and dstar [M].
+    the scene's; present: optional [N] mask of agents in the simulation.
+    Returns a dict with new_vel [M,2], vhat [M,2], nbr [M,kcap] (-1 padded),
+    n_nbr [M], status [M] (0 = 2D LP, 1 = fallback, 2 = absent) and dstar [M].
     """
     pos, vel, pref, goals = map(_f32, (pos, vel, pref, goals))
-    props, keep = _agents(radius, max_speed, pref_speed)
+    props, keep = _agents(radius, max_speed, pref_speed, present)
     n = pos.shape[1]
     offsets = np.ascontiguousarray(offsets, np.int64)
     pa = params_array(params)
@@ -238,6 +241,32 @@ def step(pos, vel, pref, offsets, params, goals=None, n_steps=1, radius=None, ma
                       len(params), _ptr(np.ascontiguousarray(offsets, np.int64)),
                       params_array(params), int(n_steps), _ptr(st))
     return pos, vel, pref, st
+
+
+def life_step(pos, vel, pref, offsets, params, goals, spawn_step, state, t0, n_steps=1,
+              radius=None, max_speed=None, pref_speed=None):
+    """Steps t0 .. t0+n_steps-1 with spawning and removal on copies of the state.
+
+    spawn_step [N] int32: the step at which each agent enters; state [N] uint8:
+    1 = removed.  Returns (pos, vel, pref, state, status of the last step)."""
+    pos = np.array(pos, np.float32, copy=True, order="C")
+    vel = np.array(vel, np.float32, copy=True, order="C")
+    pref = np.array(pref, np.float32, copy=True, order="C")
+    state = np.array(state, np.uint8, copy=True, order="C")
+    spawn = np.ascontiguousarray(spawn_step, np.int32)
+    goals = _f32(goals)
+    ag, keep = _agents(radius, max_speed, pref_speed)
+    n = pos.shape[1]
+    st = np.zeros(n, np.uint8)
+    L = lib()
+    if not hasattr(L, "_life_ready"):
+        L.oracle_life_step.argtypes = [I64, P, P, P, P, P, I32, P, P, I32, P, P, I32, P]
+        L.oracle_life_step.restype = None
+        L._life_ready = True
+    L.oracle_life_step(n, _ptr(pos), _ptr(vel), _ptr(pref), _ptr(goals), ag, len(params),
+                       _ptr(np.ascontiguousarray(offsets, np.int64)), params_array(params),
+                       int(n_steps), _ptr(spawn), _ptr(state), int(t0), _ptr(st))
+    return pos, vel, pref, state, st
 
 
 # ---------------------------------------------------------------- gradients

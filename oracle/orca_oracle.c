@@ -68,7 +68,13 @@ typedef struct {
  */
 typedef struct {
     const float *radius, *max_speed, *pref_speed;
+    const uint8_t *present; /* 0: the agent is not in the simulation (not spawned or removed) */
 } oracle_agents;
+
+static int ag_present(const oracle_agents *ag, int64_t j)
+{
+    return !(ag && ag->present) || ag->present[j] != 0;
+}
 
 static double ag_radius(const oracle_agents *ag, const oracle_params *p, int64_t i)
 {
@@ -123,16 +129,16 @@ static int cand_cmp(const void *a, const void *b)
     return (x->id > y->id) - (x->id < y->id);
 }
 
-/* Definition: all j != i of [lo,hi) with d2 < nd^2, ascending by (d2, j), first K. */
-int oracle_knn_brute(int64_t n_total, const float *pos, int64_t lo, int64_t hi, int64_t i,
-                     float nd, int32_t k, int64_t *ids, float *d2s)
+/* Definition: all present j != i of [lo,hi) with d2 < nd^2, ascending by (d2, j), first K. */
+static int knn_brute_mask(int64_t n_total, const float *pos, int64_t lo, int64_t hi, int64_t i,
+                          float nd, int32_t k, int64_t *ids, float *d2s, const uint8_t *present)
 {
     const float *x = pos, *y = pos + n_total;
     float nd2 = nd * nd;
     int64_t cap = 64, m = 0;
     cand_t *c = (cand_t *)malloc(sizeof(cand_t) * cap);
     for (int64_t j = lo; j < hi; ++j) {
-        if (j == i) continue;
+        if (j == i || (present && !present[j])) continue;
         float d2 = oracle_dist2_f32(x[i], y[i], x[j], y[j]);
         if (d2 < nd2) {
             if (m == cap) { cap *= 2; c = (cand_t *)realloc(c, sizeof(cand_t) * cap); }
@@ -146,6 +152,12 @@ int oracle_knn_brute(int64_t n_total, const float *pos, int64_t lo, int64_t hi, 
     return out;
 }
 
+int oracle_knn_brute(int64_t n_total, const float *pos, int64_t lo, int64_t hi, int64_t i,
+                     float nd, int32_t k, int64_t *ids, float *d2s)
+{
+    return knn_brute_mask(n_total, pos, lo, hi, i, nd, k, ids, d2s, NULL);
+}
+
 /* The paper's message binning: square bins of side >= nd, one list per bin. */
 typedef struct {
     double x0, y0, cell;
@@ -155,7 +167,7 @@ typedef struct {
 } bins_t;
 
 static void bins_build(bins_t *b, int64_t n_total, const float *pos, int64_t lo, int64_t hi,
-                       float nd)
+                       float nd, const uint8_t *present)
 {
     const float *x = pos, *y = pos + n_total;
     double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
@@ -175,6 +187,7 @@ static void bins_build(bins_t *b, int64_t n_total, const float *pos, int64_t lo,
     b->items = (int64_t *)malloc(sizeof(int64_t) * (size_t)(hi - lo + 1));
     int64_t *cellof = (int64_t *)malloc(sizeof(int64_t) * (size_t)(hi - lo + 1));
     for (int64_t j = lo; j < hi; ++j) {
+        if (present && !present[j]) { cellof[j - lo] = -1; continue; }
         int64_t cx = (int64_t)floor(((double)x[j] - b->x0) / b->cell);
         int64_t cy = (int64_t)floor(((double)y[j] - b->y0) / b->cell);
         if (cx >= b->nx) cx = b->nx - 1;
@@ -185,7 +198,8 @@ static void bins_build(bins_t *b, int64_t n_total, const float *pos, int64_t lo,
     for (int64_t c = 0; c < nc; ++c) b->start[c + 1] += b->start[c];
     int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc + 1));
     memcpy(fill, b->start, sizeof(int64_t) * (size_t)(nc + 1));
-    for (int64_t j = lo; j < hi; ++j) b->items[fill[cellof[j - lo]]++] = j;
+    for (int64_t j = lo; j < hi; ++j)
+        if (cellof[j - lo] >= 0) b->items[fill[cellof[j - lo]]++] = j;
     free(fill);
     free(cellof);
 }
@@ -235,7 +249,7 @@ void oracle_knn_binned_scene(int64_t n_total, const float *pos, int64_t lo, int6
                              float nd, int32_t k, int64_t *ids)
 {
     bins_t b;
-    bins_build(&b, n_total, pos, lo, hi, nd);
+    bins_build(&b, n_total, pos, lo, hi, nd, NULL);
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = lo; i < hi; ++i) {
         int64_t *row = ids + (i - lo) * k;
@@ -403,7 +417,7 @@ void oracle_velocities(int64_t n_total, const float *pos, const float *vel, cons
         bins = (bins_t *)calloc((size_t)n_scenes, sizeof(bins_t));
         for (int s = 0; s < n_scenes; ++s)
             bins_build(&bins[s], n_total, pos, offsets[s], offsets[s + 1],
-                       params[s].neighbor_dist);
+                       params[s].neighbor_dist, ag ? ag->present : NULL);
     }
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t a = 0; a < n_agents; ++a) {
@@ -412,12 +426,23 @@ void oracle_velocities(int64_t n_total, const float *pos, const float *vel, cons
         const oracle_params *p = &params[s];
         int64_t ids[64];
         int32_t m;
+        if (!ag_present(ag, i)) {
+            /* not in the simulation: no velocity, status 2 */
+            new_vel[2 * a] = new_vel[2 * a + 1] = 0.0;
+            if (vhat) { vhat[2 * a] = vhat[2 * a + 1] = 0.0; }
+            if (nbr)
+                for (int32_t t = 0; t < kcap; ++t) nbr[a * kcap + t] = -1;
+            if (n_nbr) n_nbr[a] = 0;
+            if (status) status[a] = 2;
+            if (dstar) dstar[a] = 0.0;
+            continue;
+        }
         if (neighbor_mode == 1)
             m = knn_binned(&bins[s], n_total, pos, i, p->neighbor_dist, p->max_neighbors, ids,
                            NULL);
         else
-            m = oracle_knn_brute(n_total, pos, offsets[s], offsets[s + 1], i, p->neighbor_dist,
-                                 p->max_neighbors, ids, NULL);
+            m = knn_brute_mask(n_total, pos, offsets[s], offsets[s + 1], i, p->neighbor_dist,
+                               p->max_neighbors, ids, NULL, ag ? ag->present : NULL);
         double vhx, vhy;
         if (goals)
             oracle_steer(pos[i], pos[n_total + i], goals[i], goals[n_total + i],
@@ -477,6 +502,60 @@ void oracle_step(int64_t n_total, float *pos, float *vel, float *pref, const flo
     free(vh);
 }
 
+/*
+ * Steps with spawning and removal (section 4: people enter their start
+ * region at a spawn time and are removed once they reach their goal).  At
+ * step t (t0, t0 + 1, ...) agent i is in the simulation if spawn_step[i] <= t
+ * and state[i] == 0; only those agents see each other, move and are steered.
+ * After the step an agent whose goal lies within its own radius of its new
+ * float32 position is removed (state 1).  The decision is taken in float64 on
+ * the float32 coordinates, each operation rounded on its own.
+ */
+void oracle_life_step(int64_t n_total, float *pos, float *vel, float *pref, const float *goals,
+                      const oracle_agents *ag_in, int32_t n_scenes, const int64_t *offsets,
+                      const oracle_params *params, int32_t n_steps, const int32_t *spawn_step,
+                      uint8_t *state, int32_t t0, uint8_t *status_last)
+{
+    uint8_t *present = (uint8_t *)malloc((size_t)(n_total ? n_total : 1));
+    double *nv = (double *)malloc(sizeof(double) * 2 * (size_t)(n_total ? n_total : 1));
+    double *vh = (double *)malloc(sizeof(double) * 2 * (size_t)(n_total ? n_total : 1));
+    oracle_agents ag = {NULL, NULL, NULL, present};
+    if (ag_in) {
+        ag.radius = ag_in->radius;
+        ag.max_speed = ag_in->max_speed;
+        ag.pref_speed = ag_in->pref_speed;
+    }
+    for (int32_t step = 0; step < n_steps; ++step) {
+        const int32_t t = t0 + step;
+        for (int64_t i = 0; i < n_total; ++i)
+            present[i] = (uint8_t)(spawn_step[i] <= t && state[i] == 0);
+        oracle_velocities(n_total, pos, vel, pref, goals, &ag, n_scenes, offsets, params, NULL,
+                          n_total, 1, 1, nv, vh, NULL, NULL,
+                          step == n_steps - 1 ? status_last : NULL, NULL);
+        for (int64_t i = 0; i < n_total; ++i) {
+            if (!present[i]) continue;
+            const int s = scene_of(n_scenes, offsets, i);
+            const oracle_params *p = &params[s];
+            const double dt = p->dt;
+            pos[i] = (float)((double)pos[i] + dt * nv[2 * i]);
+            pos[n_total + i] = (float)((double)pos[n_total + i] + dt * nv[2 * i + 1]);
+            vel[i] = (float)nv[2 * i];
+            vel[n_total + i] = (float)nv[2 * i + 1];
+            pref[i] = (float)vh[2 * i];
+            pref[n_total + i] = (float)vh[2 * i + 1];
+            const double ex = (double)goals[i] - (double)pos[i];
+            const double ey = (double)goals[n_total + i] - (double)pos[n_total + i];
+            const double sx = ex * ex;
+            const double sy = ey * ey;
+            const double r = ag_radius(&ag, p, i);
+            if (sx + sy <= r * r) state[i] = 1;
+        }
+    }
+    free(present);
+    free(nv);
+    free(vh);
+}
+
 /* ------------------------------------------------------------------ */
 /* Gradients (forward mode by complex step) and float64 trajectories   */
 /* ------------------------------------------------------------------ */
@@ -497,7 +576,7 @@ void oracle_step(int64_t n_total, float *pos, float *vel, float *pref, const flo
         for (int64_t i = 0; i < 2 * n; ++i) p32[i] = (float)RE_(pos[i]);                          \
         bins_t *bins = (bins_t *)calloc((size_t)n_scenes, sizeof(bins_t));                        \
         for (int s = 0; s < n_scenes; ++s)                                                        \
-            bins_build(&bins[s], n, p32, off[s], off[s + 1], par[s].neighbor_dist);               \
+            bins_build(&bins[s], n, p32, off[s], off[s + 1], par[s].neighbor_dist, NULL);         \
         _Pragma("omp parallel for schedule(dynamic, 16)")                                         \
         for (int64_t i = 0; i < n; ++i) {                                                         \
             int s = scene_of(n_scenes, off, i);                                                   \

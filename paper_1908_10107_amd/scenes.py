@@ -23,6 +23,11 @@ workloads below follow that recipe at the sizes the measurements use:
   speed (section 4): two groups swap places; per-agent radius 0.5, 0.75 or
   1 m and desired speed 1, 1.33 or 2 m/s, each equally likely, max speed 125%
   of the desired speed.
+* ``crossing_spawn`` the 2-way and 8-way crossings with people entering over
+  time and leaving at their goal (section 4): start regions spawn at a steady
+  rate, each new person clear of everyone spawned in the same region within a
+  time window set by size and speed; goals are uniform in the paired end region
+  (the other group's start region; for 8 ways, the region 135 degrees on).
 
 Every generator is deterministic in its seed (``numpy.random.default_rng``).
 """
@@ -72,6 +77,8 @@ class Workload:
     radius: Optional[np.ndarray] = None
     max_speed: Optional[np.ndarray] = None
     pref_speed: Optional[np.ndarray] = None
+    # optional step at which each agent enters [N] int32 (None: all from the start)
+    spawn_step: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
@@ -308,6 +315,70 @@ def crossing_hetero(n: int = 2500, density: float = 0.2, gap: float = 10.0, heig
     return w
 
 
+def crossing_spawn(ways: int = 2, n: int = 2500, spawn_steps: int = 400, ring: float = 40.0,
+                   region: float = 15.0, hetero: bool = False, seed: int = BASE_SEED + 6,
+                   steps: int = 3000, **over) -> Workload:
+    """2-way or 8-way crossing with spawning (section 4).
+
+    ``ways`` square start regions of side ``region`` sit on a circle of radius
+    ``ring`` (2 ways: facing each other across it).  Each spawns n / ways
+    people at a steady rate over ``spawn_steps`` steps.  A spawn point is drawn
+    uniformly in the region and redrawn while it is within r_i + r_j of anyone
+    spawned in that region too recently to have walked r_i + r_j at their
+    desired speed.  Goals are uniform in the paired end region:
+    the opposite one for 2 ways, the one 135 degrees on for 8 ways.  With
+    ``hetero`` the people draw radius and desired speed as in the second
+    variation of the 2-way crossing; otherwise they share the first variation's
+    radius 0.5 m, desired speed 1.0 m/s and max speed 1.33 m/s.
+    """
+    if ways not in (2, 8):
+        raise ValueError("ways must be 2 or 8")
+    rng = np.random.default_rng(seed)
+    kw = {**DEFAULT_PARAMS, "radius": 0.5, "max_speed": 1.33, "pref_speed": 1.0}
+    kw.update(over)
+    p = SceneParams(**kw)
+    per = n // ways
+    n = per * ways
+    if hetero:
+        radius = rng.choice(np.array([0.5, 0.75, 1.0]), n)
+        speed = rng.choice(np.array([1.0, 1.33, 2.0]), n)
+        vmax = 1.25 * speed
+    else:
+        radius = np.full(n, p.radius)
+        speed = np.full(n, p.pref_speed)
+        vmax = np.full(n, p.max_speed)
+    ang = 2.0 * np.pi * np.arange(ways) / ways
+    centres = ring * np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    end = (np.arange(ways) + (1 if ways == 2 else 3)) % ways   # 2: opposite; 8: 135 degrees
+    pos = np.zeros((n, 2))
+    goals = np.zeros((n, 2))
+    spawn = np.zeros(n, np.int32)
+    for g in range(ways):
+        idx = np.arange(g * per, (g + 1) * per)
+        spawn[idx] = (np.arange(per) * spawn_steps) // per
+        first = idx[0]
+        for i in idx:
+            # j still covers its spawn point while it has walked less than r_i + r_j
+            j = np.arange(first, i)
+            recent = j[(spawn[i] - spawn[j]) * speed[j] * p.dt < radius[i] + radius[j]]
+            for _ in range(10000):
+                q = centres[g] + (rng.random(2) - 0.5) * region
+                d = np.hypot(pos[recent, 0] - q[0], pos[recent, 1] - q[1])
+                if np.all(d >= radius[recent] + radius[i] + 1e-3):
+                    break
+            else:
+                raise RuntimeError("no free spawn point; enlarge the region or the spawn time")
+            pos[i] = q
+            goals[i] = centres[end[g]] + (rng.random(2) - 0.5) * region
+    w = _pack("crossing_spawn%d" % ways, [pos.T], [goals.T], [p], steps)
+    w.spawn_step = spawn
+    if hetero:
+        w.radius = radius.astype(np.float32)
+        w.pref_speed = speed.astype(np.float32)
+        w.max_speed = vmax.astype(np.float32)
+    return w
+
+
 def tiny_random(n: int, side: float, seed: int, vel_scale: float = 1.0, **over) -> Workload:
     """Small uniform scene with random current and preferred velocities (parity cases)."""
     rng = np.random.default_rng(seed)
@@ -327,4 +398,5 @@ WORKLOADS = {
     "batched": batched,
     "grad": grad,
     "crossing_hetero": crossing_hetero,
+    "crossing_spawn": crossing_spawn,
 }
