@@ -232,6 +232,43 @@ def hetero_forms(steps: int, launch):
                                      "agents": w.n, "steps": steps}}
 
 
+def spawn_forms(steps: int, launch):
+    """Spawning and removal (section 4) at the 1M-agent density: the dense
+    uniform square with each agent entering at a uniform step in [0, 200),
+    a goal 2-10 m away and removal on arrival; timed from step 100 (about half
+    present, arrivals under way), graph replays."""
+    import numpy as np
+    import torch
+    from paper_1908_10107_amd import orca, scenes
+    w = scenes.dense_uniform()
+    rng = np.random.default_rng(scenes.BASE_SEED + 9)
+    ang = rng.uniform(0.0, 2.0 * np.pi, w.n)
+    dist = rng.uniform(2.0, 10.0, w.n)
+    w.goals = np.ascontiguousarray(
+        (w.pos + dist * np.stack([np.cos(ang), np.sin(ang)])).astype(np.float32))
+    w.spawn_step = rng.integers(0, 200, w.n).astype(np.int32)
+    d = orca.to_device(w)
+    state = torch.zeros(w.n, dtype=torch.uint8, device="cuda")
+    ctx = orca.Context(max_agents=w.n, max_scenes=1, k_max=w.params[0].max_neighbors)
+    if launch:
+        ctx.set_launch(*launch)
+    ctx.set_lifecycle(d["spawn_step"], state, 0)
+    step = lambda k: ctx.step_graph(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"],
+                                    goals=d["goals"], n_steps=k)
+    step(100)
+    _, present0, removed0 = ctx.population()
+    t0 = time.perf_counter()
+    step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    t_end, present1, removed1 = ctx.population()
+    ctx.close()
+    return {"spawn_removal_1M": {"value": w.n * steps / dt, "ms_per_step": 1e3 * dt / steps,
+                                 "agents": w.n, "steps": steps, "first_step": 100,
+                                 "present_at_start": present0, "present_at_end": present1,
+                                 "removed_in_timed_steps": removed1 - removed0}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,10 +279,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="the CPU reference steps the workload until this much time has passed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,batched,adjoint,hetero",
+    ap.add_argument("--forms", default="plain,batched,adjoint,hetero,spawn",
                     help="comma list: plain (always), batched (512 scenes, graph replay vs "
                          "per-scene plain steps), adjoint (forward + adjoint), hetero "
-                         "(people of different sizes and speeds)")
+                         "(people of different sizes and speeds), spawn (spawning and "
+                         "removal)")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None,
@@ -340,6 +378,8 @@ def main():
         forms.update(adjoint_forms())
     if "hetero" in args.forms.split(","):
         forms.update(hetero_forms(50, tuned if args.launch else None))
+    if "spawn" in args.forms.split(","):
+        forms.update(spawn_forms(100, tuned if args.launch else None))
 
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

@@ -134,7 +134,9 @@ int orca_build_grid(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
  *             -1); the rows are packed with stride k_row = max over scenes of
  *             max_neighbors; NULL to skip;
  *   lp_status [N] uint8: 0 = the 2D program was feasible, 1 = least
- *             penetration fallback; NULL to skip.
+ *             penetration fallback, 2 = absent (spawning and removal: not
+ *             yet spawned or removed; its new_vel is 0 and its nbr_out row
+ *             all -1); NULL to skip.
  */
 int orca_compute_velocities(orca_ctx *ctx, const float *pos, const float *vel,
                             const float *pref_vel, const float *goals, float *new_vel,
@@ -193,6 +195,37 @@ int orca_autotune(orca_ctx *ctx, const float *pos, const float *vel, const float
  */
 int orca_set_agents(orca_ctx *ctx, const float *radius, const float *max_speed,
                     const float *pref_speed);
+
+/*
+ * Spawning and removal (section 4: crossings where people enter over time
+ * and leave at their goal).  spawn_step: device int32 [N], the step index at
+ * which each agent enters; state: device uint8 [N], 0 = not removed, 1 =
+ * removed, read and written by the kernels.  At step index t an agent takes
+ * part (is binned, seen as a neighbour, steered and moved) iff
+ * spawn_step[i] <= t and state[i] == 0; absent agents keep their position
+ * and velocity.  After each step's Euler update an agent whose goal lies
+ * within its own radius of its new float32 position (|g - x|^2 <= r^2 in
+ * float64) gets state 1.  The step index lives on the device: this call sets
+ * it to t0 and every orca_step / orca_step_graph step advances it by one
+ * (orca_build_grid evaluates presence at the current index without
+ * advancing), so graph replays need no host round trip.  Both NULL turns the
+ * feature off.  The context keeps the pointers (the caller keeps the arrays
+ * alive); orca_step and orca_step_graph then need goals, and recorded steps
+ * (save_tape) are refused.  Waits for the stream.  Errors: EINVAL (ctx NULL,
+ * exactly one of the arrays NULL, or later: a step without goals or with
+ * save_tape), ESTATE (profiling on).
+ */
+int orca_set_lifecycle(orca_ctx *ctx, const int32_t *spawn_step, uint8_t *state, int32_t t0);
+
+/*
+ * Read the spawning and removal counters (waits for the stream): *step = the
+ * step index the next step evaluates presence at, *present = agents present
+ * at the last binning (-1 if none has run since orca_set_lifecycle; N when
+ * the feature is off), *removed = agents removed at their goal since
+ * orca_set_lifecycle.  Each output is nullable.  Errors: EINVAL (ctx NULL),
+ * EHIP.
+ */
+int orca_population(orca_ctx *ctx, int32_t *step, int64_t *present, int64_t *removed);
 
 /*
  * Set the launch shapes directly (the two values orca_autotune picks):

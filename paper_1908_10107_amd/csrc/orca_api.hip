@@ -52,6 +52,12 @@ struct orca_ctx {
     // optional per-agent properties (caller's device arrays), see orca_set_agents
     const float *a_radius = nullptr, *a_vmax = nullptr, *a_speed = nullptr;
 
+    // spawning and removal (caller's device arrays), see orca_set_lifecycle
+    const int32_t *l_spawn = nullptr;
+    uint8_t *l_state = nullptr;
+    int32_t h_life[2] = {0, 0};  // staging of (step, removed) for the counter upload
+    bool life_binned = false;    // a binning with spawning and removal has been enqueued
+
     // scene set currently on the device
     int32_t n_scenes = 0;
     int64_t n = 0;
@@ -92,7 +98,7 @@ struct orca_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    const void *graph_key[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const void *graph_key[9] = {};
     uint64_t graph_scene_version = 0, scene_version = 0;
     int32_t graph_knn_block = 0, graph_fb = 0;
 
@@ -254,6 +260,11 @@ orca::Plan make_plan(const orca_ctx *ctx)
     p.out.ag.max_speed = ctx->a_vmax;
     p.out.ag.pref_speed = ctx->a_speed;
     p.out.ag.srad = ctx->srad;
+    p.out.life.spawn_step = ctx->l_spawn;
+    p.out.life.state = ctx->l_state;
+    p.out.life.sp = ctx->sp;
+    p.out.life.agent_scene = ctx->agent_scene;
+    p.out.life.counters = ctx->counters;
     return p;
 }
 
@@ -268,7 +279,10 @@ orca::Plan make_plan(const orca_ctx *ctx)
 int run_pass(orca_ctx *ctx, const orca::Plan &pl, const float *grid_pos, const float *grid_vel)
 {
     STAGE_MARK(0);
-    if (grid_pos) HIP_OK(orca::launch_grid(pl, grid_pos, grid_vel, ctx->stream));
+    if (grid_pos) {
+        HIP_OK(orca::launch_grid(pl, grid_pos, grid_vel, true, ctx->stream));
+        if (ctx->l_spawn) ctx->life_binned = true;
+    }
     STAGE_MARK(1);
     HIP_OK(orca::launch_knn(pl, ctx->kmax_cur, ctx->stream));
     STAGE_MARK(2);
@@ -342,8 +356,9 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
     ctx->stream = (hipStream_t)hip_stream;
     // cell budget: room for 4 cells per agent plus a margin per scene
     const int64_t cells = 4 * max_agents + 64 * (int64_t)max_scenes + 4096;
-    ctx->max_cells = (uint32_t)(cells < (int64_t)INT32_MAX - 1 ? cells : (int64_t)INT32_MAX - 1);
-    ctx->n_tiles = (int32_t)((ctx->max_cells + orca::kScanTile - 1) / orca::kScanTile);
+    ctx->max_cells = (uint32_t)(cells < (int64_t)INT32_MAX - 2 ? cells : (int64_t)INT32_MAX - 2);
+    // the scan also covers the cell of absent agents (spawning and removal)
+    ctx->n_tiles = (int32_t)((ctx->max_cells + 1 + orca::kScanTile - 1) / orca::kScanTile);
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t prop;
@@ -372,8 +387,8 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->counters, sizeof(Counters)) &&
               alloc((void **)&ctx->key, sizeof(int32_t) * A) &&
               alloc((void **)&ctx->rank, sizeof(int32_t) * A) &&
-              alloc((void **)&ctx->counts, sizeof(int32_t) * C) &&
-              alloc((void **)&ctx->cell_start, sizeof(int32_t) * (C + 1)) &&
+              alloc((void **)&ctx->counts, sizeof(int32_t) * (C + 1)) &&
+              alloc((void **)&ctx->cell_start, sizeof(int32_t) * (C + 2)) &&
               alloc((void **)&ctx->partial, sizeof(uint32_t) * (size_t)ctx->n_tiles) &&
               alloc((void **)&ctx->sorted, sizeof(float4) * A) &&
               alloc((void **)&ctx->sid, sizeof(int32_t) * A) &&
@@ -400,7 +415,7 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
         return ORCA_ENOMEM;
     }
     // counts start at zero and are kept zero between uses by the scan
-    hipError_t e = hipMemsetAsync(ctx->counts, 0, sizeof(int32_t) * C, ctx->stream);
+    hipError_t e = hipMemsetAsync(ctx->counts, 0, sizeof(int32_t) * (C + 1), ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->counters, 0, sizeof(Counters), ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->acc, 0, sizeof(double) * 4 * A, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->acc_scene, 0, sizeof(double) * 2 * S, ctx->stream);
@@ -439,7 +454,8 @@ int orca_build_grid(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
     if (rc != ORCA_OK) return rc;
     if (!pos && ctx->n > 0) return fail(ctx, ORCA_EINVAL, "pos must be non-NULL");
     const orca::Plan pl = make_plan(ctx);
-    HIP_OK(orca::launch_grid(pl, pos, nullptr, ctx->stream));
+    HIP_OK(orca::launch_grid(pl, pos, nullptr, false, ctx->stream));
+    if (ctx->l_spawn) ctx->life_binned = true;
     ctx->grid_valid = true;
     ctx->grid_pos = pos;
     ctx->grid_radius = ctx->a_radius;
@@ -453,6 +469,48 @@ int orca_set_agents(orca_ctx *ctx, const float *radius, const float *max_speed,
     ctx->a_radius = radius;
     ctx->a_vmax = max_speed;
     ctx->a_speed = pref_speed;
+    return ORCA_OK;
+}
+
+int orca_set_lifecycle(orca_ctx *ctx, const int32_t *spawn_step, uint8_t *state, int32_t t0)
+{
+    if (!ctx) return ORCA_EINVAL;
+    if ((spawn_step == nullptr) != (state == nullptr))
+        return fail(ctx, ORCA_EINVAL, "spawn_step and state must both be given or both be NULL");
+    if (ctx->profiling) return fail(ctx, ORCA_ESTATE, "stop profiling before setting up spawning");
+    ctx->l_spawn = spawn_step;
+    ctx->l_state = state;
+    ctx->grid_valid = false;
+    ctx->life_binned = false;
+    // step <- t0, removed <- 0 (the staging words stay valid until the copy is done)
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    ctx->h_life[0] = spawn_step ? t0 : 0;
+    ctx->h_life[1] = 0;
+    HIP_OK(hipMemcpyAsync(&ctx->counters->step, ctx->h_life, sizeof(ctx->h_life),
+                          hipMemcpyHostToDevice, ctx->stream));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    return ORCA_OK;
+}
+
+int orca_population(orca_ctx *ctx, int32_t *step, int64_t *present, int64_t *removed)
+{
+    if (!ctx) return ORCA_EINVAL;
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    Counters c;
+    HIP_OK(hipMemcpy(&c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost));
+    int64_t np = ctx->n;
+    if (ctx->l_spawn) {
+        np = -1;
+        if (ctx->life_binned && c.total_cells >= 1) {
+            int32_t v = 0;
+            HIP_OK(hipMemcpy(&v, ctx->cell_start + (c.total_cells - 1), sizeof(v),
+                             hipMemcpyDeviceToHost));
+            np = v;
+        }
+    }
+    if (step) *step = ctx->l_spawn ? c.step : 0;
+    if (present) *present = np;
+    if (removed) *removed = ctx->l_spawn ? (int64_t)c.removed : 0;
     return ORCA_OK;
 }
 
@@ -489,7 +547,11 @@ int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
     if (rc != ORCA_OK) return rc;
     if (ctx->n > 0 && (!pos || !vel || !pref_vel))
         return fail(ctx, ORCA_EINVAL, "pos, vel and pref_vel must be non-NULL");
+    if (ctx->l_spawn && !goals)
+        return fail(ctx, ORCA_EINVAL, "spawning and removal need goals");
     if (save_tape) {
+        if (ctx->l_spawn)
+            return fail(ctx, ORCA_EINVAL, "a recorded step cannot use spawning and removal");
         if (goals) return fail(ctx, ORCA_EINVAL, "a recorded step needs fixed preferred velocities");
         if (n_steps > ctx->tape_steps)
             return fail(ctx, ORCA_ECAPACITY, "n_steps %d exceeds tape_steps %d", n_steps,
@@ -534,8 +596,11 @@ int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
     if (rc != ORCA_OK) return rc;
     if (ctx->n > 0 && (!pos || !vel || !pref_vel))
         return fail(ctx, ORCA_EINVAL, "pos, vel and pref_vel must be non-NULL");
+    if (ctx->l_spawn && !goals)
+        return fail(ctx, ORCA_EINVAL, "spawning and removal need goals");
     ctx->grid_valid = false;
-    const void *key[7] = {pos, vel, pref_vel, goals, ctx->a_radius, ctx->a_vmax, ctx->a_speed};
+    const void *key[9] = {pos,           vel,         pref_vel,     goals,      ctx->a_radius,
+                          ctx->a_vmax,   ctx->a_speed, ctx->l_spawn, ctx->l_state};
     const bool fresh = ctx->graph_exec && memcmp(key, ctx->graph_key, sizeof(key)) == 0 &&
                        ctx->graph_scene_version == ctx->scene_version &&
                        ctx->graph_knn_block == ctx->knn_block &&

@@ -31,10 +31,16 @@ struct GridDev {
     int32_t nx, ny, base, pad;
 };
 
+// Device-side counters of the context.  total_cells counts the grid cells of
+// every scene plus, with spawning and removal on, one last cell that holds the
+// absent agents (so cell_start of that cell is the number of present agents).
+// step is the step index the next binning evaluates presence at; removed
+// counts agents removed at their goal since spawning and removal were set up.
 struct Counters {
     uint32_t total_cells;
     uint32_t n_fallback;
-    uint32_t pad[2];
+    int32_t step;
+    uint32_t removed;
 };
 
 // An agent whose projection was empty, with what the fallback needs to
@@ -98,6 +104,17 @@ struct AgentProps {
     float *srad;
 };
 
+// Spawning and removal (caller's device arrays): agent i takes part in the
+// step at index t when spawn_step[i] <= t and state[i] == 0; a step that ends
+// with the agent's goal within its own radius sets state[i] = 1.
+struct LifeArgs {
+    const int32_t *spawn_step;  // [N] or nullptr (off)
+    uint8_t *state;             // [N]
+    const SceneDev *sp;         // scene radius, when no per-agent radius is given
+    const int32_t *agent_scene;
+    Counters *counters;
+};
+
 // Where the velocity kernels put their results.  Step mode has pos != nullptr.
 struct OutArgs {
     float *new_vel;      // [2, N] or nullptr
@@ -111,6 +128,7 @@ struct OutArgs {
     float4 *tape_state;  // recorded step: state (x, y, vx, vy) at the step's start, or nullptr
     TapeCode *tape_codes;  // recorded step: how each velocity was chosen
     AgentProps ag;         // per-agent properties of this pass
+    LifeArgs life;         // spawning and removal (life.spawn_step == nullptr: off)
 };
 
 // Device buffers and sizes of one launch sequence.
@@ -142,7 +160,9 @@ struct Plan {
 
 hipError_t launch_scene_map(const int32_t *off, int32_t n_scenes, int32_t *agent_scene, int32_t n,
                             uint32_t *bbox, hipStream_t st);
-hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, hipStream_t st);
+// advance: move the step counter on (a step with spawning and removal)
+hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, bool advance,
+                       hipStream_t st);
 hipError_t launch_fill_vel(const Plan &pl, const float *vel, hipStream_t st);
 hipError_t launch_knn(const Plan &pl, int kmax, hipStream_t st);
 hipError_t launch_lp(const Plan &pl, int kmax, hipStream_t st);

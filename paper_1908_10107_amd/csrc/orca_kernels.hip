@@ -5,7 +5,8 @@
 //   k_grid        per-scene cell size / origin / dimensions and the cell-key
 //                 base of every scene (one block)
 //   k_key         cell key of every agent and its rank inside the cell
-//                 (histogram by atomic increment)
+//                 (histogram by atomic increment); with spawning and removal,
+//                 absent agents go to one extra cell sorted after every scene
 //   k_scan_sums   per-tile sums of the cell counts
 //   k_scan_apply  exclusive scan -> cell_start, counts cleared for the next step
 //   k_scatter     counting-sort scatter: agents into cell order (float4 x,y,vx,vy)
@@ -153,13 +154,16 @@ __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ pos, int
 // wide, so two agents closer than neighbor_dist (also after float32 rounding
 // of their squared distance) always sit in the same or adjacent cells.  If the
 // total number of cells would exceed the budget, all cells are widened by a
-// common factor (more candidates per agent, same neighbours).  Also resets
-// the bounding-box accumulators and the fallback counter for the next use.
+// common factor (more candidates per agent, same neighbours).  With spawning
+// and removal on (life), one more cell after all scenes' cells takes the
+// absent agents.  Also resets the bounding-box accumulators and the fallback
+// counter for the next use.
 __global__ __launch_bounds__(256) void k_grid(int32_t n_scenes, const int32_t *__restrict__ off,
                                               const SceneDev *__restrict__ sp,
                                               uint32_t *__restrict__ bbox,
                                               GridDev *__restrict__ grid,
-                                              Counters *__restrict__ counters, uint32_t max_cells)
+                                              Counters *__restrict__ counters, uint32_t max_cells,
+                                              int32_t life)
 {
     __shared__ unsigned long long red[4];
     double f = 1.0;
@@ -209,7 +213,7 @@ __global__ __launch_bounds__(256) void k_grid(int32_t n_scenes, const int32_t *_
             grid[s].base = (int32_t)base;
             base += (uint32_t)grid[s].nx * (uint32_t)grid[s].ny;
         }
-        counters->total_cells = base;
+        counters->total_cells = base + (life ? 1u : 0u);
         counters->n_fallback = 0;
     }
     __syncthreads();
@@ -221,15 +225,27 @@ __global__ __launch_bounds__(256) void k_grid(int32_t n_scenes, const int32_t *_
     }
 }
 
+// Cell key of every agent; an absent agent (not yet spawned at the step
+// counters->step, or removed) goes to the last cell, so it sorts after every
+// present agent and no cell of a scene holds it.
 __global__ __launch_bounds__(256) void k_key(const float *__restrict__ pos, int32_t n,
                                              const int32_t *__restrict__ agent_scene,
                                              const GridDev *__restrict__ grid,
                                              int32_t *__restrict__ key,
                                              int32_t *__restrict__ rank,
-                                             int32_t *__restrict__ counts)
+                                             int32_t *__restrict__ counts,
+                                             const int32_t *__restrict__ spawn_step,
+                                             const uint8_t *__restrict__ state,
+                                             const Counters *__restrict__ counters)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (spawn_step && (spawn_step[i] > counters->step || state[i] != 0)) {
+        const int32_t k = (int32_t)counters->total_cells - 1;
+        key[i] = k;
+        rank[i] = atomicAdd(&counts[k], 1);
+        return;
+    }
     const GridDev g = grid[agent_scene[i]];
     double fx = floor(((double)pos[i] - g.x0) / g.cell);
     double fy = floor(((double)pos[n + i] - g.y0) / g.cell);
@@ -268,18 +284,23 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_sums(const int32_t *__restr
 }
 
 // cell_start[c] = sum of counts before c; cell_start[total] = n.  Counts are
-// zeroed after reading so the next histogram starts from zero.
+// zeroed after reading so the next histogram starts from zero.  In a step
+// with spawning and removal (advance), the step counter moves on here: k_key,
+// its only reader, has finished.
 __global__ __launch_bounds__(kScanBlock) void k_scan_apply(int32_t *__restrict__ counts,
-                                                           const Counters *__restrict__ counters,
+                                                           Counters *__restrict__ counters,
                                                            const uint32_t *__restrict__ partial,
                                                            int32_t *__restrict__ cell_start,
-                                                           int32_t n)
+                                                           int32_t n, int32_t advance)
 {
     __shared__ uint32_t wsum[kScanBlock / 64];
     __shared__ uint32_t s_prefix;
     const uint32_t total = counters->total_cells;
     const uint32_t base = blockIdx.x * kScanTile;
-    if (blockIdx.x == 0 && threadIdx.x == 0) cell_start[total] = n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cell_start[total] = n;
+        if (advance) counters->step += 1;
+    }
     if (base >= total) return;
     // prefix of the earlier tiles
     uint32_t p = 0;
@@ -406,12 +427,14 @@ __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
                                              const SceneDev *__restrict__ sp, int32_t n,
                                              int32_t *__restrict__ nbr, int32_t ld,
                                              int32_t *__restrict__ ncount,
-                                             Counters *__restrict__ counters)
+                                             Counters *__restrict__ counters, int32_t life)
 {
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     // the fallback list of this velocity pass starts empty (k_lp runs after us)
     if (s == 0) counters->n_fallback = 0;
-    if (s >= n) return;
+    // absent agents sit in the last cell, after every present one
+    const int32_t n_present = life ? cell_start[counters->total_cells - 1] : n;
+    if (s >= n_present) return;
     const float4 me = sorted[s];
     const int32_t myid = sid[s];
     const int32_t sc = agent_scene[myid];
@@ -623,6 +646,11 @@ __device__ __forceinline__ void preferred_velocity(const SceneDev &p, const Agen
     }
 }
 
+// Kernel variants: plain, recording a tape for the adjoint, or with spawning
+// and removal (which never records).
+constexpr int kModePlain = 0, kModeRec = 1, kModeLife = 2;
+
+template <bool LIFE>
 __device__ __forceinline__ void write_result(const OutArgs &o, float mex, float mey, float dtf,
                                              int32_t id, int32_t n, double vx, double vy,
                                              double vhx, double vhy, uint8_t status)
@@ -634,13 +662,29 @@ __device__ __forceinline__ void write_result(const OutArgs &o, float mex, float 
     }
     if (o.pos) {
         const double dt = (double)dtf;
-        o.pos[id] = (float)((double)mex + dt * vx);
-        o.pos[n + id] = (float)((double)mey + dt * vy);
+        const float px = (float)((double)mex + dt * vx);
+        const float py = (float)((double)mey + dt * vy);
+        o.pos[id] = px;
+        o.pos[n + id] = py;
         o.vel[id] = (float)vx;
         o.vel[n + id] = (float)vy;
         if (o.goals) {
             o.pref[id] = (float)vhx;
             o.pref[n + id] = (float)vhy;
+        }
+        if (LIFE) {
+            // removed once the goal lies within the agent's own radius of its
+            // new position (float64 on the float32 coordinates)
+            const double ex = (double)o.goals[id] - (double)px;
+            const double ey = (double)o.goals[n + id] - (double)py;
+            const double sx = ex * ex;
+            const double sy = ey * ey;
+            const double r = (double)(o.ag.radius ? o.ag.radius[id]
+                                                  : o.life.sp[o.life.agent_scene[id]].radius);
+            if (sx + sy <= r * r) {
+                o.life.state[id] = 1;
+                atomicAdd(&o.life.counters->removed, 1u);
+            }
         }
     }
     if (o.status) o.status[id] = status;
@@ -651,7 +695,7 @@ __device__ __forceinline__ void write_result(const OutArgs &o, float mex, float 
 // handed to the fallback list with everything
 // k_fallback needs (one atomic per wave): its record, its sort key (the failed
 // row) and its half-planes in stash slot `slot`, in stash_position order.
-template <int KMAX, bool REC>
+template <int KMAX, int MODE>
 __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sorted,
                                                  const int32_t *__restrict__ sid,
                                                  const int32_t *__restrict__ agent_scene,
@@ -662,8 +706,10 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
                                                  uint8_t *__restrict__ fb_key, int32_t kcap,
                                                  double2 *__restrict__ stash_n,
                                                  double *__restrict__ stash_b,
-                                                 Counters *__restrict__ counters)
+                                                 Counters *__restrict__ counters,
+                                                 const int32_t *__restrict__ cell_start)
 {
+    constexpr bool REC = MODE == kModeRec, LIFE = MODE == kModeLife;
     constexpr bool kRegs = KMAX <= kLpRegRows;
     __shared__ double2 s_n[kRegs ? 1 : KMAX * kLpBlock];
     __shared__ double s_b[kRegs ? 1 : KMAX * kLpBlock];
@@ -672,7 +718,21 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
     if constexpr (!kRegs) rows.L = Lane{s_n + threadIdx.x, s_b + threadIdx.x};
     bool need_fb = false;
     FallbackItem it{};
-    if (s < n) {
+    // absent agents (spawning and removal) sit after every present one
+    const int32_t n_present = LIFE ? cell_start[counters->total_cells - 1] : n;
+    if (LIFE && s >= n_present && s < n) {
+        // not in the simulation this step: status 2, zero velocity, no neighbours;
+        // a step leaves its position and velocity as they are
+        const int32_t id = sid[s];
+        if (out.new_vel) {
+            out.new_vel[id] = 0.f;
+            out.new_vel[n + id] = 0.f;
+        }
+        if (out.status) out.status[id] = 2;
+        if (out.nbr_out)
+            for (int k = 0; k < out.krow; ++k) out.nbr_out[(int64_t)id * out.krow + k] = -1;
+    }
+    if (s < n_present) {
         const float4 me = sorted[s];
         const int32_t id = sid[s];
         const SceneDev p = sp[agent_scene[id]];
@@ -688,7 +748,7 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
         const int fail = rows.project(m, vmax, vhx, vhy, vx, vy, &act);
         if (REC) out.tape_state[id] = me;
         if (fail < 0) {
-            write_result(out, me.x, me.y, p.dt, id, n, vx, vy, vhx, vhy, 0);
+            write_result<LIFE>(out, me.x, me.y, p.dt, id, n, vx, vy, vhx, vhy, 0);
             if (REC) {
                 TapeCode tc{};
                 tc.status = 0;
@@ -839,7 +899,7 @@ struct FbRows<KMAX, false> {
 };
 
 // The persistent loop of k_fallback over its share of the sorted list.
-template <int KMAX, bool REC, class RS>
+template <int KMAX, int MODE, class RS>
 __device__ __forceinline__ void fallback_items(RS &rows, const OutArgs &out, int32_t n, int32_t kcap,
                                                const FallbackItem *__restrict__ fb_list,
                                                const int32_t *__restrict__ fb_order,
@@ -894,7 +954,7 @@ __device__ __forceinline__ void fallback_items(RS &rows, const OutArgs &out, int
             vx = wx;
             vy = wy;
         }
-        if (REC) {
+        if (MODE == kModeRec) {
             TapeCode tc{};
             tc.status = 1;
             tc.p_line = (int8_t)stash_row(ract.line, it);
@@ -906,7 +966,8 @@ __device__ __forceinline__ void fallback_items(RS &rows, const OutArgs &out, int
             tc.dstar = d;
             out.tape_codes[it.id] = tc;
         }
-        write_result(out, it.mex, it.mey, it.dt, it.id, n, vx, vy, it.vhx, it.vhy, 1);
+        write_result<MODE == kModeLife>(out, it.mex, it.mey, it.dt, it.id, n, vx, vy, it.vhx,
+                                        it.vhy, 1);
     }
 }
 
@@ -916,7 +977,7 @@ __device__ __forceinline__ void fallback_items(RS &rows, const OutArgs &out, int
 // vhat among those within d* + delta of every half-plane, with the rows that
 // fix d* taken first: the relaxed projection's optimum lies where they cross,
 // so the other rows are rarely violated.
-template <int KMAX, bool REC>
+template <int KMAX, int MODE>
 __global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, int32_t kcap,
                                                        const FallbackItem *__restrict__ fb_list,
                                                        const int32_t *__restrict__ fb_order,
@@ -931,10 +992,10 @@ __global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, i
     double rnx[kRegs ? KMAX : 1], rny[kRegs ? KMAX : 1], rb[kRegs ? KMAX : 1];
     if constexpr (kRegs) {
         FbRows<KMAX> rows{rnx, rny, rb};
-        fallback_items<KMAX, REC>(rows, out, n, kcap, fb_list, fb_order, stash_n, stash_b, count);
+        fallback_items<KMAX, MODE>(rows, out, n, kcap, fb_list, fb_order, stash_n, stash_b, count);
     } else {
         FbRows<KMAX> rows{Lane{s_n + threadIdx.x, s_b + threadIdx.x}};
-        fallback_items<KMAX, REC>(rows, out, n, kcap, fb_list, fb_order, stash_n, stash_b, count);
+        fallback_items<KMAX, MODE>(rows, out, n, kcap, fb_list, fb_order, stash_n, stash_b, count);
     }
 }
 
@@ -947,47 +1008,59 @@ hipError_t launch_knn_k(const Plan &pl, hipStream_t st)
     const int32_t bs = pl.knn_block;
     hipLaunchKernelGGL(k_knn<KMAX>, dim3((n + bs - 1) / bs), dim3(bs), 0, st, pl.sorted, pl.sid,
                        pl.skey, pl.inv, pl.cell_start, pl.grid, pl.agent_scene, pl.sp, n, pl.nbr, pl.ld,
-                       pl.ncount, pl.counters);
+                       pl.ncount, pl.counters, pl.out.life.spawn_step ? 1 : 0);
     return hipGetLastError();
 }
 
-template <int KMAX, bool REC>
-hipError_t launch_lp_rec(const Plan &pl, hipStream_t st)
+template <int KMAX, int MODE>
+hipError_t launch_lp_mode(const Plan &pl, hipStream_t st)
 {
     const int32_t n = pl.n;
     const int32_t gl = (n + kLpBlock - 1) / kLpBlock;
-    hipLaunchKernelGGL((k_lp<KMAX, REC>), dim3(gl), dim3(kLpBlock), 0, st, pl.sorted, pl.sid,
+    hipLaunchKernelGGL((k_lp<KMAX, MODE>), dim3(gl), dim3(kLpBlock), 0, st, pl.sorted, pl.sid,
                        pl.agent_scene, pl.sp, n, pl.nbr, pl.ld, pl.ncount, pl.out, pl.fb_list,
-                       pl.fb_key, pl.kcap, pl.stash_n, pl.stash_b, pl.counters);
+                       pl.fb_key, pl.kcap, pl.stash_n, pl.stash_b, pl.counters, pl.cell_start);
     return hipGetLastError();
 }
 
-template <int KMAX, bool REC>
-hipError_t launch_fallback_rec(const Plan &pl, hipStream_t st)
+template <int KMAX, int MODE>
+hipError_t launch_fallback_mode(const Plan &pl, hipStream_t st)
 {
     // persistent: fb_waves_per_cu one-wave blocks per CU loop over the device-side list
     const int32_t gs = (pl.n + kFbSortChunk - 1) / kFbSortChunk;
     hipLaunchKernelGGL(k_fb_sort, dim3(gs), dim3(kFbSortBlock), 0, st, pl.fb_key, pl.fb_order,
                        pl.counters);
     const int32_t gf = max(1, min((pl.n + kLpBlock - 1) / kLpBlock, pl.fb_waves_per_cu * pl.cus));
-    hipLaunchKernelGGL((k_fallback<KMAX, REC>), dim3(gf), dim3(kLpBlock), 0, st, pl.out, pl.n,
+    hipLaunchKernelGGL((k_fallback<KMAX, MODE>), dim3(gf), dim3(kLpBlock), 0, st, pl.out, pl.n,
                        pl.kcap, pl.fb_list, pl.fb_order, pl.stash_n, pl.stash_b, pl.counters);
     return hipGetLastError();
 }
 
-// Recording (for the adjoint) is a separate instantiation: the plain one
-// carries none of its bookkeeping.
+// Recording (for the adjoint) and spawning / removal are separate
+// instantiations: the plain one carries none of their bookkeeping.
+inline int plan_mode(const Plan &pl)
+{
+    return pl.out.tape_codes ? kModeRec : (pl.out.life.spawn_step ? kModeLife : kModePlain);
+}
+
 template <int KMAX>
 hipError_t launch_lp_k(const Plan &pl, hipStream_t st)
 {
-    return pl.out.tape_codes ? launch_lp_rec<KMAX, true>(pl, st) : launch_lp_rec<KMAX, false>(pl, st);
+    switch (plan_mode(pl)) {
+    case kModeRec: return launch_lp_mode<KMAX, kModeRec>(pl, st);
+    case kModeLife: return launch_lp_mode<KMAX, kModeLife>(pl, st);
+    default: return launch_lp_mode<KMAX, kModePlain>(pl, st);
+    }
 }
 
 template <int KMAX>
 hipError_t launch_fallback_k(const Plan &pl, hipStream_t st)
 {
-    return pl.out.tape_codes ? launch_fallback_rec<KMAX, true>(pl, st)
-                             : launch_fallback_rec<KMAX, false>(pl, st);
+    switch (plan_mode(pl)) {
+    case kModeRec: return launch_fallback_mode<KMAX, kModeRec>(pl, st);
+    case kModeLife: return launch_fallback_mode<KMAX, kModeLife>(pl, st);
+    default: return launch_fallback_mode<KMAX, kModePlain>(pl, st);
+    }
 }
 
 // The neighbour-list length picks the register / LDS footprint.
@@ -1015,22 +1088,28 @@ hipError_t launch_scene_map(const int32_t *off, int32_t n_scenes, int32_t *agent
     return hipGetLastError();
 }
 
-hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, hipStream_t st)
+hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, bool advance,
+                       hipStream_t st)
 {
     const int32_t n = pl.n;
+    const LifeArgs &life = pl.out.life;
     if (n > 0)
         hipLaunchKernelGGL(k_bbox, dim3(pl.n_chunks), dim3(256), 0, st, pos, n, pl.chunks,
                            pl.off, pl.bbox);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, pl.n_scenes, pl.off, pl.sp, pl.bbox,
-                       pl.grid, pl.counters, pl.max_cells);
-    if (n == 0) return hipGetLastError();
-    hipLaunchKernelGGL(k_key, dim3((n + 255) / 256), dim3(256), 0, st, pos, n, pl.agent_scene,
-                       pl.grid, pl.key, pl.rank, pl.counts);
-    const int32_t tiles = (int32_t)((pl.max_cells + kScanTile - 1) / kScanTile);
+                       pl.grid, pl.counters, pl.max_cells, life.spawn_step ? 1 : 0);
+    if (n > 0)
+        hipLaunchKernelGGL(k_key, dim3((n + 255) / 256), dim3(256), 0, st, pos, n,
+                           pl.agent_scene, pl.grid, pl.key, pl.rank, pl.counts, life.spawn_step,
+                           life.state, pl.counters);
+    // the scan covers the scenes' cells and the cell of absent agents
+    const int32_t tiles = (int32_t)((pl.max_cells + 1 + kScanTile - 1) / kScanTile);
     hipLaunchKernelGGL(k_scan_sums, dim3(tiles), dim3(kScanBlock), 0, st, pl.counts, pl.counters,
                        pl.partial);
     hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kScanBlock), 0, st, pl.counts,
-                       pl.counters, pl.partial, pl.cell_start, n);
+                       pl.counters, pl.partial, pl.cell_start, n,
+                       advance && life.spawn_step ? 1 : 0);
+    if (n == 0) return hipGetLastError();
     hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, st, pos, vel, n, pl.key,
                        pl.rank, pl.cell_start, pl.sorted, pl.sid, pl.skey, pl.inv,
                        pl.out.ag.radius, pl.out.ag.srad);

@@ -84,6 +84,10 @@ def load(path: str = LIB_PATH):
     L.orca_set_launch.restype = ctypes.c_int
     L.orca_set_agents.argtypes = [_P, _P, _P, _P]
     L.orca_set_agents.restype = ctypes.c_int
+    L.orca_set_lifecycle.argtypes = [_P, _P, _P, ctypes.c_int32]
+    L.orca_set_lifecycle.restype = ctypes.c_int
+    L.orca_population.argtypes = [_P, _P, _P, _P]
+    L.orca_population.restype = ctypes.c_int
     L.orca_profile.argtypes = [_P, ctypes.c_int32]
     L.orca_profile.restype = ctypes.c_int
     L.orca_profile_read.argtypes = [_P, _P, _P, _P]
@@ -227,6 +231,32 @@ class Context:
         self._check(self.lib.orca_set_agents(self.h, *ptrs))
         self._agents = (radius, max_speed, pref_speed)
 
+    def set_lifecycle(self, spawn_step=None, state=None, t0=0):
+        """Spawning and removal (see orca_set_lifecycle): spawn_step [N] int32 and
+        state [N] uint8 CUDA tensors (state is updated in place), step index t0.
+        Pass nothing to turn it off.  The tensors are kept referenced here."""
+        ptrs = []
+        for t, nm, dt in ((spawn_step, "spawn_step", self._torch.int32),
+                          (state, "state", self._torch.uint8)):
+            if t is None:
+                ptrs.append(None)
+                continue
+            if not (t.is_cuda and t.dtype == dt and t.dim() == 1 and t.is_contiguous()):
+                raise TypeError("%s must be a contiguous 1-D %s CUDA tensor" % (nm, dt))
+            ptrs.append(ctypes.c_void_p(t.data_ptr()))
+        self._sync_stream()
+        self._check(self.lib.orca_set_lifecycle(self.h, ptrs[0], ptrs[1], int(t0)))
+        self._life = (spawn_step, state)
+
+    def population(self):
+        """(step, present, removed) from the device counters (see orca_population)."""
+        st = ctypes.c_int32()
+        pr, rm = ctypes.c_int64(), ctypes.c_int64()
+        self._sync_stream()
+        self._check(self.lib.orca_population(self.h, ctypes.byref(st), ctypes.byref(pr),
+                                             ctypes.byref(rm)))
+        return st.value, pr.value, rm.value
+
     def set_launch(self, knn_block, fallback_waves_per_cu):
         """Fix the launch shapes that autotune would pick (see orca_set_launch)."""
         self._check(self.lib.orca_set_launch(self.h, int(knn_block), int(fallback_waves_per_cu)))
@@ -285,4 +315,5 @@ def to_device(w, device="cuda"):
     t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)
     return dict(pos=t(w.pos), vel=t(w.vel), pref_vel=t(w.pref_vel), goals=t(w.goals),
                 radius=t(getattr(w, "radius", None)), max_speed=t(getattr(w, "max_speed", None)),
-                pref_speed=t(getattr(w, "pref_speed", None)))
+                pref_speed=t(getattr(w, "pref_speed", None)),
+                spawn_step=t(getattr(w, "spawn_step", None)))

@@ -315,14 +315,18 @@ def crossing_hetero(n: int = 2500, density: float = 0.2, gap: float = 10.0, heig
     return w
 
 
-def crossing_spawn(ways: int = 2, n: int = 2500, spawn_steps: int = 400, ring: float = 40.0,
-                   region: float = 15.0, hetero: bool = False, seed: int = BASE_SEED + 6,
-                   steps: int = 3000, **over) -> Workload:
+def crossing_spawn(ways: int = 2, n: int = 2500, spawn_steps: Optional[int] = None,
+                   ring: Optional[float] = None, region: Optional[float] = None,
+                   hetero: bool = False, seed: int = BASE_SEED + 6, steps: int = 6000,
+                   **over) -> Workload:
     """2-way or 8-way crossing with spawning (section 4).
 
     ``ways`` square start regions of side ``region`` sit on a circle of radius
     ``ring`` (2 ways: facing each other across it).  Each spawns n / ways
-    people at a steady rate over ``spawn_steps`` steps.  A spawn point is drawn
+    people at a steady rate over ``spawn_steps`` steps.  Defaults: a 40 m
+    region, a 50 m ring and 1500 steps for 2 ways, a 20 m region, a 50 m ring
+    and 1000 steps for 8 (about 8 people a second per region: a crowd that
+    clears in a few thousand steps).  A spawn point is drawn
     uniformly in the region and redrawn while it is within r_i + r_j of anyone
     spawned in that region too recently to have walked r_i + r_j at their
     desired speed.  Goals are uniform in the paired end region:
@@ -333,6 +337,9 @@ def crossing_spawn(ways: int = 2, n: int = 2500, spawn_steps: int = 400, ring: f
     """
     if ways not in (2, 8):
         raise ValueError("ways must be 2 or 8")
+    spawn_steps = spawn_steps or (1500 if ways == 2 else 1000)
+    ring = ring or 50.0
+    region = region or (40.0 if ways == 2 else 20.0)
     rng = np.random.default_rng(seed)
     kw = {**DEFAULT_PARAMS, "radius": 0.5, "max_speed": 1.33, "pref_speed": 1.0}
     kw.update(over)

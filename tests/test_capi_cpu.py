@@ -53,6 +53,8 @@ def test_null_context_calls(lib):
     assert lib.orca_set_stream(None, None) == orca.EINVAL
     assert lib.orca_set_launch(None, 256, 16) == orca.EINVAL
     assert lib.orca_set_agents(None, None, None, None) == orca.EINVAL
+    assert lib.orca_set_lifecycle(None, None, None, 0) == orca.EINVAL
+    assert lib.orca_population(None, None, None, None) == orca.EINVAL
     lib.orca_destroy(None)
 
 
