@@ -10,9 +10,11 @@
 //   k_scan_sums   per-tile sums of the cell counts
 //   k_scan_apply  exclusive scan -> cell_start, counts cleared for the next step
 //   k_scatter     counting-sort scatter: agents into cell order (float4 x,y,vx,vy)
-//   k_knn         3x3-cell gather, K nearest by float32 squared distance held as
+//   k_knn         gather over the cells within neighbor_dist (each row over the
+//                 disc's chord), K nearest by float32 squared distance held as
 //                 packed 64-bit keys in registers
-//   k_lp          float64 half-planes in LDS, incremental 2D LP; feasible agents
+//   k_lp          float64 half-planes in registers (LDS above 16 rows),
+//                 incremental 2D LP; feasible agents
 //                 write their result, the rest are appended to a fallback list
 //   k_fallback    persistent over the fallback list: least-penetration 3D LP,
 //                 then the 2D LP on the relaxed half-planes
@@ -388,13 +390,15 @@ __global__ __launch_bounds__(256) void k_fill_vel(const float *__restrict__ vel,
 
 // ------------------------------------------------------------------ neighbours
 
-// Offer a (d2 bits << 32 | id) key to the sorted list best[0..K) whose K-th
-// entry is `worst`.
+// The running neighbour list of one lane: KMAX sorted 64-bit keys
+// (d2 bits << 32 | id + 1).  For K < KMAX the first KMAX - K slots hold the
+// key 0, below every real key, so the K nearest always sit in the last K
+// slots and the K-th is best[KMAX - 1] whatever K is.  Unfilled slots hold
+// ~0.  Offer key to the list.
 template <int KMAX>
-__device__ __forceinline__ void knn_offer(uint64_t (&best)[KMAX], uint64_t &worst, int32_t K,
-                                          uint64_t key)
+__device__ __forceinline__ void knn_offer(uint64_t (&best)[KMAX], uint64_t key)
 {
-    if (key >= worst) return;
+    if (key >= best[KMAX - 1]) return;
 #pragma unroll
     for (int k = KMAX - 1; k > 0; --k) {
         const bool shift = key < best[k - 1];
@@ -402,20 +406,59 @@ __device__ __forceinline__ void knn_offer(uint64_t (&best)[KMAX], uint64_t &wors
         best[k] = shift ? best[k - 1] : (here ? key : best[k]);
     }
     best[0] = key < best[0] ? key : best[0];
-    if (K == KMAX) {
-        worst = best[KMAX - 1];
-    } else {
+}
+
+// Offer the candidates [i, ie) of one row run (sorted indices) to the sorted
+// key list.  lim is the largest float32 bit pattern of d2 that can still
+// enter: strictly inside neighbor_dist and no farther than the list's K-th
+// entry (d2 >= 0, so the bit patterns order like the values; a NaN's pattern
+// exceeds every limit).  The agent itself (id myid) is skipped when it comes
+// up for insertion.
+template <int KMAX>
+__device__ __forceinline__ void knn_run(uint64_t (&best)[KMAX], uint32_t &lim, uint32_t nd_lim,
+                                        float mx, float my, uint32_t myid, int32_t i, int32_t ie,
+                                        const float4 *__restrict__ sorted,
+                                        const int32_t *__restrict__ sid)
+{
+    auto offer = [&](uint32_t hi, uint32_t id) __attribute__((always_inline)) {
+        if (id == myid) return;
+        knn_offer<KMAX>(best, ((uint64_t)hi << 32) | (id + 1u));
+        lim = min(nd_lim, (uint32_t)(best[KMAX - 1] >> 32));
+    };
+    // candidates kBatch at a time: their positions and ids are loaded
+    // together, so one memory latency covers the batch
+    constexpr int kBatch = KMAX <= 16 ? 4 : 2;
+    for (; i + kBatch <= ie; i += kBatch) {
+        float4 o[kBatch];
+        uint32_t idb[kBatch];
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-            if (k == K - 1) worst = best[k];
+        for (int u = 0; u < kBatch; ++u) o[u] = sorted[i + u];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) idb[u] = (uint32_t)sid[i + u];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const uint32_t hi = __float_as_uint(dist2_f32(mx, my, o[u].x, o[u].y));
+            if (hi <= lim) offer(hi, idb[u]);
+        }
+    }
+    for (; i < ie; ++i) {
+        const float4 o = sorted[i];
+        const uint32_t hi = __float_as_uint(dist2_f32(mx, my, o.x, o.y));
+        if (hi <= lim) offer(hi, (uint32_t)sid[i]);
     }
 }
 
-// K nearest of each agent (sorted order s) among the agents of its 3x3 cells,
-// strictly inside neighbor_dist, nearest first, ties by agent id.  The running
-// list holds (float32 bits of d2) << 32 | id, so one 64-bit compare orders by
-// (d2, id).  Writes nbr[k * ld + s] = the neighbour's sorted index, with bit
-// 31 set when the neighbour's id is the smaller of the pair, and ncount[s].
+// K nearest of each agent (sorted order s) among the agents of the cells
+// within neighbor_dist, strictly inside it, nearest first, ties by agent id.
+// Writes nbr[k * ld + s] = the neighbour's sorted index, with bit 31 set when
+// the neighbour's id is the smaller of the pair, and ncount[s].
+//
+// Each row within reach is read over the cells its chord of the disc touches
+// (one contiguous run of sorted indices), own row first.  Cells are about
+// nd/2 wide, so the disc of radius nd reaches two rows and columns out (one
+// once the grid was widened to nd).  The chord is taken a little wider than
+// nd, so rounding of the cell arithmetic or of the float32 distance never
+// drops a neighbour: the distance test decides.
 template <int KMAX>
 __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
                                              const int32_t *__restrict__ sid,
@@ -441,22 +484,20 @@ __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
     const GridDev g = grid[sc];
     const int32_t K = sp[sc].k;
     const float nd2 = sp[sc].nd2;
-    if (K == 0) {
+    // d2 < nd2 as bit patterns: at most the pattern just below nd2's (an nd2
+    // that underflowed to zero admits nobody)
+    if (K == 0 || !(nd2 > 0.0f)) {
         ncount[s] = 0;
         return;
     }
+    const uint32_t nd_lim = __float_as_uint(nd2) - 1u;
+    uint32_t lim = nd_lim;
     const int32_t c = skey[s] - g.base;
     const int32_t cy = c / g.nx, cx = c - cy * g.nx;
     uint64_t best[KMAX];
+    const int32_t pad = KMAX - K;  // leading slots that hold the key 0
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) best[k] = ~0ull;
-    uint64_t worst = ~0ull;  // current K-th entry
-    // Cells are about nd/2 wide, so the disc of radius nd reaches two rows and
-    // columns out (one once the grid was widened to nd).  Each row is read over
-    // the cells its chord of the disc touches (one contiguous run of sorted
-    // indices), own row first.  The chord is taken a little wider than nd, so
-    // rounding of the cell arithmetic or of the float32 distance never drops a
-    // neighbour: the distance test below decides.
+    for (int k = 0; k < KMAX; ++k) best[k] = k < pad ? 0ull : ~0ull;
     const double cell = g.cell, nd = (double)sp[sc].nd;
     const int32_t reach = cell >= nd ? 1 : 2;
     const double px = (double)me.x, py = (double)me.y;
@@ -475,41 +516,18 @@ __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
                                min(cx + reach, g.nx - 1));
         if (c0 > c1) continue;
         const int32_t rb = g.base + row * g.nx;
-        const int32_t beg = cell_start[rb + c0], end = cell_start[rb + c1 + 1];
-        // candidates kBatch at a time: their positions and ids are loaded
-        // together, so one memory latency covers the batch
-        constexpr int kBatch = KMAX <= 16 ? 4 : 2;
-        int32_t j = beg;
-        for (; j + kBatch <= end; j += kBatch) {
-            float4 o[kBatch];
-            uint32_t idb[kBatch];
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) o[u] = sorted[j + u];
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) idb[u] = (uint32_t)sid[j + u];
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const float d2 = dist2_f32(me.x, me.y, o[u].x, o[u].y);
-                if (d2 < nd2 && j + u != s)
-                    knn_offer<KMAX>(best, worst, K, ((uint64_t)__float_as_uint(d2) << 32) | idb[u]);
-            }
-        }
-        for (; j < end; ++j) {
-            const float4 o = sorted[j];
-            const float d2 = dist2_f32(me.x, me.y, o.x, o.y);
-            if (d2 < nd2 && j != s)
-                knn_offer<KMAX>(best, worst, K, ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)sid[j]);
-        }
+        knn_run<KMAX>(best, lim, nd_lim, me.x, me.y, (uint32_t)myid, cell_start[rb + c0],
+                      cell_start[rb + c1 + 1], sorted, sid);
     }
     int32_t cnt = 0;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        if (k < K && best[k] != ~0ull) {
-            const uint32_t jid = (uint32_t)(best[k] & 0xffffffffu);
+        if (k >= pad && best[k] != ~0ull) {
+            const uint32_t jid = (uint32_t)(best[k] & 0xffffffffu) - 1u;
             // bit 31: this agent does not come first of the pair (ids order it)
             const uint32_t later = (uint32_t)myid < jid ? 0u : 0x80000000u;
-            nbr[(int64_t)k * ld + s] = (int32_t)((uint32_t)inv[jid] | later);
-            cnt = k + 1;
+            nbr[(int64_t)(k - pad) * ld + s] = (int32_t)((uint32_t)inv[jid] | later);
+            cnt = k - pad + 1;
         }
     }
     ncount[s] = cnt;

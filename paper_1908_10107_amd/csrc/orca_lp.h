@@ -124,7 +124,6 @@ struct Active {
 struct Interval {
     double lo_n, lo_d, hi_n, hi_d;
     int lo_src, hi_src;
-    bool bad;
     ORCA_HDI inline void init(double h_n, double h_d)
     {
         lo_n = -h_n;
@@ -133,23 +132,24 @@ struct Interval {
         hi_d = h_d;
         lo_src = kSrcDisc;
         hi_src = kSrcDisc;
-        bad = false;
     }
-    // add s * den >= num (row src)
+    // add s * den >= num (row src).  A row parallel to the line (den == 0)
+    // that excludes it (num > 0) raises the lower end to num / 0 = +infinity
+    // (lo_d = 0), which every later row keeps and empty() reports; one that
+    // admits it (num <= 0) changes nothing.
     ORCA_HDI inline void add(double den, double num, int src)
     {
-        const bool up = den > 0.0, down = den < 0.0;
+        const bool up = den >= 0.0;
         const bool raise = up && num * lo_d > lo_n * den;
-        const bool lower = down && num * hi_d > hi_n * den;  // num/den < hi, den < 0
+        const bool lower = !up && num * hi_d > hi_n * den;  // num/den < hi, den < 0
         lo_n = raise ? num : lo_n;
         lo_d = raise ? den : lo_d;
         lo_src = raise ? src : lo_src;
         hi_n = lower ? -num : hi_n;
         hi_d = lower ? -den : hi_d;
         hi_src = lower ? src : hi_src;
-        bad = bad | (!up & !down & (num > 0.0));
     }
-    ORCA_HDI inline bool empty() const { return bad || lo_n * hi_d > hi_n * lo_d; }
+    ORCA_HDI inline bool empty() const { return lo_n * hi_d > hi_n * lo_d; }
     // t_n / t_d clamped into the interval (t_d > 0); returns the source that
     // bounds the result (kSrcFree if t was inside)
     ORCA_HDI inline int clamp(double t_n, double t_d, double &o_n, double &o_d) const
