@@ -67,14 +67,14 @@ static_assert(sizeof(FallbackItem) == 64, "one fallback record per 64-byte line"
 // program meets few violations after its first plane.
 __host__ __device__ __forceinline__ int stash_position(int k, const FallbackItem &it)
 {
+    // selects only: the kernels evaluate it for every row of a wave at once
     const int fail = it.fail, line = it.line, src = it.src, worst = it.worst;
-    if (k < fail) {
-        const int nf = (line >= 0 ? 1 : 0) + (src >= 0 ? 1 : 0);
-        if (k == line) return 0;
-        if (k == src) return line >= 0 ? 1 : 0;
-        return nf + k - ((src >= 0 && src < k) ? 1 : 0) - ((line >= 0 && line < k) ? 1 : 0);
-    }
-    return k == worst ? fail : k + (k < worst ? 1 : 0);
+    const int nf = (line >= 0 ? 1 : 0) + (src >= 0 ? 1 : 0);
+    int before = nf + k - ((src >= 0 && src < k) ? 1 : 0) - ((line >= 0 && line < k) ? 1 : 0);
+    before = k == src ? (line >= 0 ? 1 : 0) : before;
+    before = k == line ? 0 : before;
+    const int after = k == worst ? fail : k + (k < worst ? 1 : 0);
+    return k < fail ? before : after;
 }
 
 // Inverse of stash_position (negative codes pass through: they name no row).

@@ -118,18 +118,20 @@ struct Active {
 };
 
 // Feasible interval lo <= s <= hi of a 1D program, each end kept as a
-// fraction with a positive denominator and compared by cross-multiplication,
-// so adding a constraint costs no division.  lo_src / hi_src name the row
-// that set each end (kSrcDisc for the disc).
+// fraction and compared by cross-multiplication, so adding a constraint costs
+// no division.  lo has a non-negative denominator, hi a negative one (as the
+// rows that set it come), so neither end is ever negated.  lo_src / hi_src
+// name the row that set each end (kSrcDisc for the disc).
 struct Interval {
     double lo_n, lo_d, hi_n, hi_d;
     int lo_src, hi_src;
+    // -h_n / h_d <= s <= h_n / h_d, h_d > 0
     ORCA_HDI inline void init(double h_n, double h_d)
     {
         lo_n = -h_n;
         lo_d = h_d;
-        hi_n = h_n;
-        hi_d = h_d;
+        hi_n = -h_n;
+        hi_d = -h_d;
         lo_src = kSrcDisc;
         hi_src = kSrcDisc;
     }
@@ -141,17 +143,18 @@ struct Interval {
     {
         const bool up = den >= 0.0;
         const bool raise = up && num * lo_d > lo_n * den;
-        const bool lower = !up && num * hi_d > hi_n * den;  // num/den < hi, den < 0
+        const bool lower = !up && num * hi_d < hi_n * den;  // num/den < hi; den, hi_d < 0
         lo_n = raise ? num : lo_n;
         lo_d = raise ? den : lo_d;
         lo_src = raise ? src : lo_src;
-        hi_n = lower ? -num : hi_n;
-        hi_d = lower ? -den : hi_d;
+        hi_n = lower ? num : hi_n;
+        hi_d = lower ? den : hi_d;
         hi_src = lower ? src : hi_src;
     }
-    ORCA_HDI inline bool empty() const { return lo_n * hi_d > hi_n * lo_d; }
+    // lo > hi (lo_d >= 0 > hi_d; lo = +infinity also counts)
+    ORCA_HDI inline bool empty() const { return lo_n * hi_d < hi_n * lo_d; }
     // t_n / t_d clamped into the interval (t_d > 0); returns the source that
-    // bounds the result (kSrcFree if t was inside)
+    // bounds the result (kSrcFree if t was inside); o_n / o_d is the value
     ORCA_HDI inline int clamp(double t_n, double t_d, double &o_n, double &o_d) const
     {
         if (t_n * lo_d < lo_n * t_d) {
@@ -159,7 +162,7 @@ struct Interval {
             o_d = lo_d;
             return lo_src;
         }
-        if (t_n * hi_d > hi_n * t_d) {
+        if (t_n * hi_d < hi_n * t_d) {
             o_n = hi_n;
             o_d = hi_d;
             return hi_src;
