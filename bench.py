@@ -350,8 +350,8 @@ def main():
         others[orca.STAGE_NAMES[i]] = {"bound": b_, "achieved": round(a_, 4), "unit": u_,
                                        "frac": round(a_ / p_, 6)}
     kdisp = 10 if kmax <= 10 else (16 if kmax <= 16 else 32)
-    kname = ("k_key", "k_knn<%d>" % kdisp, "k_lp<%d,false>" % kdisp,
-             "k_fallback<%d,false>" % kdisp)[dom]
+    kname = ("k_key", "k_knn<%d>" % kdisp, "k_lp<%d,0>" % kdisp,
+             "k_fallback<%d,0>" % kdisp)[dom]
     traffic = profiled_traffic(kname) if args.workload == "dense_uniform" else None
     roofline = dict(bound=bound, achieved=round(achieved, 4), peak=peak, unit=unit,
                     frac=round(achieved / peak, 6), traffic=traffic, traffic_unit="B/launch",

@@ -221,9 +221,9 @@ int orca_set_lifecycle(orca_ctx *ctx, const int32_t *spawn_step, uint8_t *state,
  * Read the spawning and removal counters (waits for the stream): *step = the
  * step index the next step evaluates presence at, *present = agents present
  * at the last binning (-1 if none has run since orca_set_lifecycle; N when
- * the feature is off), *removed = agents removed at their goal since
- * orca_set_lifecycle.  Each output is nullable.  Errors: EINVAL (ctx NULL),
- * EHIP.
+ * the feature is off), *removed = agents whose state is 1 (counted by a small
+ * kernel on the context stream for this call; 0 when the feature is off).
+ * Each output is nullable.  Errors: EINVAL (ctx NULL), EHIP.
  */
 int orca_population(orca_ctx *ctx, int32_t *step, int64_t *present, int64_t *removed);
 

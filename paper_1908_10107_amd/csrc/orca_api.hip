@@ -55,7 +55,7 @@ struct orca_ctx {
     // spawning and removal (caller's device arrays), see orca_set_lifecycle
     const int32_t *l_spawn = nullptr;
     uint8_t *l_state = nullptr;
-    int32_t h_life[2] = {0, 0};  // staging of (step, removed) for the counter upload
+    int32_t h_life = 0;          // staging of the step index for the counter upload
     bool life_binned = false;    // a binning with spawning and removal has been enqueued
 
     // scene set currently on the device
@@ -482,11 +482,10 @@ int orca_set_lifecycle(orca_ctx *ctx, const int32_t *spawn_step, uint8_t *state,
     ctx->l_state = state;
     ctx->grid_valid = false;
     ctx->life_binned = false;
-    // step <- t0, removed <- 0 (the staging words stay valid until the copy is done)
+    // step <- t0 (the staging word stays valid until the copy is done)
     HIP_OK(hipStreamSynchronize(ctx->stream));
-    ctx->h_life[0] = spawn_step ? t0 : 0;
-    ctx->h_life[1] = 0;
-    HIP_OK(hipMemcpyAsync(&ctx->counters->step, ctx->h_life, sizeof(ctx->h_life),
+    ctx->h_life = spawn_step ? t0 : 0;
+    HIP_OK(hipMemcpyAsync(&ctx->counters->step, &ctx->h_life, sizeof(ctx->h_life),
                           hipMemcpyHostToDevice, ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));
     return ORCA_OK;
@@ -495,6 +494,9 @@ int orca_set_lifecycle(orca_ctx *ctx, const int32_t *spawn_step, uint8_t *state,
 int orca_population(orca_ctx *ctx, int32_t *step, int64_t *present, int64_t *removed)
 {
     if (!ctx) return ORCA_EINVAL;
+    if (ctx->l_spawn && ctx->n > 0)
+        HIP_OK(orca::launch_count_removed(ctx->l_state, (int32_t)ctx->n, ctx->counters,
+                                          ctx->stream));
     HIP_OK(hipStreamSynchronize(ctx->stream));
     Counters c;
     HIP_OK(hipMemcpy(&c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost));

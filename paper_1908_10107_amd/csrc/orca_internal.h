@@ -34,8 +34,8 @@ struct GridDev {
 // Device-side counters of the context.  total_cells counts the grid cells of
 // every scene plus, with spawning and removal on, one last cell that holds the
 // absent agents (so cell_start of that cell is the number of present agents).
-// step is the step index the next binning evaluates presence at; removed
-// counts agents removed at their goal since spawning and removal were set up.
+// step is the step index the next binning evaluates presence at; removed is
+// written on request (the agents whose state is 1).
 struct Counters {
     uint32_t total_cells;
     uint32_t n_fallback;
@@ -164,6 +164,8 @@ hipError_t launch_scene_map(const int32_t *off, int32_t n_scenes, int32_t *agent
 hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, bool advance,
                        hipStream_t st);
 hipError_t launch_fill_vel(const Plan &pl, const float *vel, hipStream_t st);
+hipError_t launch_count_removed(const uint8_t *state, int32_t n, Counters *counters,
+                                hipStream_t st);
 hipError_t launch_knn(const Plan &pl, int kmax, hipStream_t st);
 hipError_t launch_lp(const Plan &pl, int kmax, hipStream_t st);
 hipError_t launch_fallback(const Plan &pl, int kmax, hipStream_t st);

@@ -229,7 +229,8 @@ __global__ __launch_bounds__(256) void k_grid(int32_t n_scenes, const int32_t *_
 
 // Cell key of every agent; an absent agent (not yet spawned at the step
 // counters->step, or removed) goes to the last cell, so it sorts after every
-// present agent and no cell of a scene holds it.
+// present agent and no cell of a scene holds it.  That cell can hold most of
+// the agents, so its ranks are taken with one atomic per wave.
 __global__ __launch_bounds__(256) void k_key(const float *__restrict__ pos, int32_t n,
                                              const int32_t *__restrict__ agent_scene,
                                              const GridDev *__restrict__ grid,
@@ -241,13 +242,26 @@ __global__ __launch_bounds__(256) void k_key(const float *__restrict__ pos, int3
                                              const Counters *__restrict__ counters)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (spawn_step && (spawn_step[i] > counters->step || state[i] != 0)) {
-        const int32_t k = (int32_t)counters->total_cells - 1;
-        key[i] = k;
-        rank[i] = atomicAdd(&counts[k], 1);
-        return;
+    const bool valid = i < n;
+    bool absent = false;
+    if (spawn_step) {  // the same on every lane
+        if (valid) absent = spawn_step[i] > counters->step || state[i] != 0;
+        const uint64_t m = __ballot(absent);
+        if (m) {
+            const int32_t k = (int32_t)counters->total_cells - 1;
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            int32_t base = 0;
+            if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(&counts[k], __popcll(m));
+            base = __shfl(base, leader, 64);
+            if (absent) {
+                const int32_t before = (int32_t)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                key[i] = k;
+                rank[i] = base + before;
+            }
+        }
     }
+    if (!valid || absent) return;
     const GridDev g = grid[agent_scene[i]];
     double fx = floor(((double)pos[i] - g.x0) / g.cell);
     double fy = floor(((double)pos[n + i] - g.y0) / g.cell);
@@ -699,10 +713,7 @@ __device__ __forceinline__ void write_result(const OutArgs &o, float mex, float 
             const double sy = ey * ey;
             const double r = (double)(o.ag.radius ? o.ag.radius[id]
                                                   : o.life.sp[o.life.agent_scene[id]].radius);
-            if (sx + sy <= r * r) {
-                o.life.state[id] = 1;
-                atomicAdd(&o.life.counters->removed, 1u);
-            }
+            if (sx + sy <= r * r) o.life.state[id] = 1;
         }
     }
     if (o.status) o.status[id] = status;
@@ -1017,6 +1028,19 @@ __global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, i
     }
 }
 
+// Number of removed agents (state 1) into counters->removed: one block.
+__global__ __launch_bounds__(256) void k_count_removed(const uint8_t *__restrict__ state,
+                                                       int32_t n, Counters *__restrict__ counters)
+{
+    __shared__ uint32_t red[4];
+    uint32_t c = 0;
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) c += state[i] == 1 ? 1u : 0u;
+    c = wave_reduce_sum_u32(c);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) counters->removed = red[0] + red[1] + red[2] + red[3];
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <int KMAX>
@@ -1131,6 +1155,13 @@ hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, bool 
     hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, st, pos, vel, n, pl.key,
                        pl.rank, pl.cell_start, pl.sorted, pl.sid, pl.skey, pl.inv,
                        pl.out.ag.radius, pl.out.ag.srad);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_removed(const uint8_t *state, int32_t n, Counters *counters,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL(k_count_removed, dim3(1), dim3(256), 0, st, state, n, counters);
     return hipGetLastError();
 }
 
