@@ -513,7 +513,10 @@ __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) best[k] = k < pad ? 0ull : ~0ull;
     const double cell = g.cell, nd = (double)sp[sc].nd;
-    const int32_t reach = cell >= nd ? 1 : 2;
+    // rows and columns the disc of radius nd can reach: nd / cell rounded up
+    // (cells are a little wider than nd / kCellsPerNd, or wider still once the
+    // grid was widened)
+    const int32_t reach = max(1, min(kCellsPerNd, (int32_t)ceil(nd / cell)));
     const double px = (double)me.x, py = (double)me.y;
     const double ndx = nd * (1.0 + 1e-6) + 1e-9 * (1.0 + fabs(px) + fabs(py));
     for (int32_t q = 0; q <= 2 * reach; ++q) {
