@@ -324,9 +324,10 @@ def crossing_spawn(ways: int = 2, n: int = 2500, spawn_steps: Optional[int] = No
     ``ways`` square start regions of side ``region`` sit on a circle of radius
     ``ring`` (2 ways: facing each other across it).  Each spawns n / ways
     people at a steady rate over ``spawn_steps`` steps.  Defaults: a 40 m
-    region, a 50 m ring and 1500 steps for 2 ways, a 20 m region, a 50 m ring
-    and 1000 steps for 8 (about 8 people a second per region: a crowd that
-    clears in a few thousand steps).  A spawn point is drawn
+    region, a 50 m ring and 3000 steps for 2 ways, a 20 m region, a 50 m ring
+    and 1000 steps for 8 (about 4 and 3 people a second per region: crowds
+    dense enough to form lanes, sparse enough to clear in a few thousand
+    steps).  A spawn point is drawn
     uniformly in the region and redrawn while it is within r_i + r_j of anyone
     spawned in that region too recently to have walked r_i + r_j at their
     desired speed.  Goals are uniform in the paired end region:
@@ -337,7 +338,7 @@ def crossing_spawn(ways: int = 2, n: int = 2500, spawn_steps: Optional[int] = No
     """
     if ways not in (2, 8):
         raise ValueError("ways must be 2 or 8")
-    spawn_steps = spawn_steps or (1500 if ways == 2 else 1000)
+    spawn_steps = spawn_steps or (3000 if ways == 2 else 1000)
     ring = ring or 50.0
     region = region or (40.0 if ways == 2 else 20.0)
     rng = np.random.default_rng(seed)

@@ -19,6 +19,8 @@ import pytest
 import oracle
 from paper_1908_10107_amd import scenes
 
+from crowd_measures import lane_order, turning_speed
+
 pytestmark = pytest.mark.gpu
 
 TOL_V = 1e-4
@@ -238,3 +240,41 @@ def test_life_argument_errors():
 def ctypes_ptr(t):
     import ctypes
     return ctypes.c_void_p(t.data_ptr())
+
+
+def test_crossing_lanes_and_turning_on_the_gpu():
+    """The crowd phenomena of section 4 in GPU runs: lanes in the 2-way
+    crossing (band order above that of shuffled groups from step 1000 to
+    3000) and one turning sense in the 8-way crossing while people cross in
+    numbers."""
+    torch = _torch()
+    say("case life lanes and vortex")
+    w = scenes.crossing_spawn(ways=2)
+    ctx, d = setup(w, torch)
+    group = (w.goals[0] < 0).astype(int)
+    rng = np.random.default_rng(0)
+    real, mixed = [], []
+    for t in range(0, 3000, 100):
+        ctx.step_graph(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], goals=d["goals"],
+                       n_steps=100)
+        if t + 100 >= 1000:
+            pos = d["pos"].cpu().numpy()
+            present = (w.spawn_step <= t + 99) & (d["state"].cpu().numpy() == 0)
+            real.append(lane_order(pos, present, group))
+            mixed.append(np.mean([lane_order(pos, present, rng.permutation(group))
+                                  for _ in range(4)]))
+    say("  lanes: band order %.3f, shuffled %.3f" % (np.mean(real), np.mean(mixed)))
+    assert np.mean(real) > np.mean(mixed) + 0.1
+    ctx.close()
+    w = scenes.crossing_spawn(ways=8)
+    ctx, d = setup(w, torch)
+    lz = []
+    for t in range(0, 2000, 100):
+        ctx.step_graph(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], goals=d["goals"],
+                       n_steps=100)
+        present = (w.spawn_step <= t + 99) & (d["state"].cpu().numpy() == 0)
+        if present.sum() >= w.n // 3:
+            lz.append(turning_speed(d["pos"].cpu().numpy(), d["vel"].cpu().numpy(), present))
+    say("  turning speed %.3f .. %.3f m/s over %d samples" % (min(lz), max(lz), len(lz)))
+    assert len(lz) >= 8 and min(lz) > 0.25
+    ctx.close()

@@ -11,12 +11,17 @@
   * the scene generator never places a new person on top of someone spawned
     in the same region who cannot yet have walked clear;
   * a small 2-way and 8-way crossing run until everyone has arrived, with no
-    two present agents that both solved the 2D LP ending a step overlapped.
+    two present agents that both solved the 2D LP ending a step overlapped;
+  * the crowd phenomena the paper reports, as measures: lanes in the 2-way
+    crossing (a band order parameter above that of shuffled groups) and one
+    turning sense in the 8-way crossing (a vortex about the centre).
 """
 import numpy as np
 import pytest
 
 from paper_1908_10107_amd import scenes
+
+from crowd_measures import lane_order, turning_speed
 
 
 def lone(goal, radius=0.5, speed=1.0, dt=0.25, spawn=0):
@@ -162,3 +167,43 @@ def test_small_crossing_runs_until_everyone_arrives(oracle_lib, ways):
             break
     assert entered.all() and state.all(), (t, int(state.sum()))
     assert np.all(np.hypot(*(w.goals - pos)) <= p.radius)
+
+
+def test_two_way_crossing_forms_lanes(oracle_lib):
+    # section 4: the two crowds pass amongst each other in lanes.  From step
+    # 1000 to 3000, the band order of the real groups beats that of the same
+    # people with their groups shuffled.
+    w = scenes.crossing_spawn(ways=2)
+    group = (w.goals[0] < 0).astype(int)
+    rng = np.random.default_rng(0)
+    pos, vel, pref = w.pos, w.vel, w.pref_vel
+    state = np.zeros(w.n, np.uint8)
+    real, mixed = [], []
+    for t in range(0, 3000, 100):
+        pos, vel, pref, state, _ = oracle_lib.life_step(pos, vel, pref, w.offsets, w.params,
+                                                        w.goals, w.spawn_step, state, t,
+                                                        n_steps=100)
+        if t + 100 >= 1000:
+            present = (w.spawn_step <= t + 99) & (state == 0)
+            real.append(lane_order(pos, present, group))
+            mixed.append(np.mean([lane_order(pos, present, rng.permutation(group))
+                                  for _ in range(4)]))
+    assert np.mean(real) > np.mean(mixed) + 0.1, (np.mean(real), np.mean(mixed))
+
+
+def test_eight_way_crossing_turns_one_way(oracle_lib):
+    # section 4: every crowd crosses 135 degrees on, so the crowd as a whole
+    # turns about the centre in one sense (a vortex): its angular momentum
+    # about the centre keeps one sign while people are crossing.
+    w = scenes.crossing_spawn(ways=8)
+    pos, vel, pref = w.pos, w.vel, w.pref_vel
+    state = np.zeros(w.n, np.uint8)
+    lz = []
+    for t in range(0, 2000, 100):
+        pos, vel, pref, state, _ = oracle_lib.life_step(pos, vel, pref, w.offsets, w.params,
+                                                        w.goals, w.spawn_step, state, t,
+                                                        n_steps=100)
+        present = (w.spawn_step <= t + 99) & (state == 0)
+        if present.sum() >= w.n // 3:   # people crossing in numbers
+            lz.append(turning_speed(pos, vel, present))
+    assert len(lz) >= 8 and min(lz) > 0.25, lz
