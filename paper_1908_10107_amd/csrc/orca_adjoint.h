@@ -45,7 +45,8 @@ struct RowGeom {
 
 ORCA_HD inline void row_geom(RowGeom &g, double R, double tau, double dt, double vix, double viy)
 {
-    obstacle_exit(g.Px, g.Py, g.Vx, g.Vy, R, tau, dt, g.first != 0, g.ux, g.uy, g.nx, g.ny);
+    obstacle_exit(g.Px, g.Py, g.Vx, g.Vy, R, tau, dt, 1.0 / tau, 1.0 / dt, g.first != 0, g.ux,
+                  g.uy, g.nx, g.ny);
     const double qx = vix + 0.5 * g.ux, qy = viy + 0.5 * g.uy;
     g.b = g.nx * qx + g.ny * qy;
 }

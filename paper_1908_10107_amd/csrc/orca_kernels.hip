@@ -615,6 +615,7 @@ __device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t 
     // combined radius r_i + r_j (section 4: people of different sizes)
     const double ri = (double)(ag.radius ? ag.radius[id] : p.radius);
     const double tau = (double)p.tau, dt = (double)p.dt;
+    const double inv_tau = 1.0 / tau, inv_dt = 1.0 / dt;  // shared by every row
     const double vix = (double)me.z, viy = (double)me.w;
 #pragma unroll
     for (int k0 = 0; k0 < KMAX; k0 += G) {
@@ -641,7 +642,8 @@ __device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t 
                 const double Px = (double)o[u].x - (double)me.x, Py = (double)o[u].y - (double)me.y;
                 const double Vx = vix - (double)o[u].z, Vy = viy - (double)o[u].w;
                 double ux, uy, nx, ny;
-                obstacle_exit(Px, Py, Vx, Vy, ri + (double)rj[u], tau, dt, e[u] >= 0, ux, uy, nx, ny);
+                obstacle_exit(Px, Py, Vx, Vy, ri + (double)rj[u], tau, dt, inv_tau, inv_dt,
+                              e[u] >= 0, ux, uy, nx, ny);
                 const double qx = vix + 0.5 * ux, qy = viy + 0.5 * uy;
                 nk = make_double2(nx, ny);
                 bk = nx * qx + ny * qy;

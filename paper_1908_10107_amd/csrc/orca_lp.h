@@ -40,13 +40,27 @@ constexpr int kLpStride = 64;  // lanes per LP block: element k of a lane at [k 
 constexpr int kLpStride = ORCA_LP_STRIDE;
 #endif
 
+// a / b rounded to nearest, from y = 1 / b rounded to nearest: one residual
+// step on a * y (Markstein's correction), exact for operands that neither
+// overflow nor underflow on the way.  A zero a keeps its sign.  Cheaper than a
+// full division when y serves several quotients.
+ORCA_HDI inline double div_recip(double a, double b, double y)
+{
+    const double q = a * y;
+    const double r = fma(fma(-q, b, a), y, q);
+    return q == 0.0 ? q : r;
+}
+
 // Shortest change u of the relative velocity V = v_i - v_j out of the velocity
 // obstacle of neighbour j (relative position P = x_j - x_i, combined radius R,
 // look-ahead tau) and the outward normal n at V + u (Fig. 1(b)-(c)).  A pair
-// already closer than R uses the one-step disc D(P/dt, R/dt).  No fused
-// multiply-add: the operations are rounded one by one.
+// already closer than R uses the one-step disc D(P/dt, R/dt).  inv_tau and
+// inv_dt are 1/tau and 1/dt rounded to nearest.  No other fused multiply-add:
+// the operations are rounded one by one, each quotient as a division would
+// round it.
 ORCA_HD inline void obstacle_exit(double Px, double Py, double Vx, double Vy, double R,
-                                              double tau, double dt, bool i_first, double &ux,
+                                              double tau, double dt, double inv_tau,
+                                              double inv_dt, bool i_first, double &ux,
                                               double &uy, double &nx, double &ny)
 {
 #pragma clang fp contract(off)
@@ -59,15 +73,16 @@ ORCA_HD inline void obstacle_exit(double Px, double Py, double Vx, double Vy, do
     const double dist2 = Px * Px + Py * Py;
     const double R2 = R * R;
     const bool apart = dist2 > R2;
-    const double tc = apart ? tau : dt;
-    const double wx = Vx - Px / tc, wy = Vy - Py / tc;
+    const double tc = apart ? tau : dt, ic = apart ? inv_tau : inv_dt;
+    const double wx = Vx - div_recip(Px, tc, ic), wy = Vy - div_recip(Py, tc, ic);
     const double w2 = wx * wx + wy * wy;
     const double wP = wx * Px + wy * Py;
     if (!apart || (wP < 0.0 && wP * wP > R2 * w2)) {
         const double wl = sqrt(w2);
         if (wl > 0.0) {
-            nx = wx / wl;
-            ny = wy / wl;
+            const double iw = 1.0 / wl;
+            nx = div_recip(wx, wl, iw);
+            ny = div_recip(wy, wl, iw);
         } else if (dist2 > 0.0) {
             // in contact and not moving apart: away from the neighbour
             const double pl = sqrt(dist2);
@@ -77,7 +92,7 @@ ORCA_HD inline void obstacle_exit(double Px, double Py, double Vx, double Vy, do
             nx = i_first ? 1.0 : -1.0;
             ny = 0.0;
         }
-        const double f = R / tc - wl;
+        const double f = div_recip(R, tc, ic) - wl;
         ux = f * nx;
         uy = f * ny;
         return;
@@ -85,8 +100,9 @@ ORCA_HD inline void obstacle_exit(double Px, double Py, double Vx, double Vy, do
     // nearest boundary point on a tangent leg: left (sg = +1) if w is left of P
     const double L = sqrt(dist2 - R2);
     const double sg = Px * wy - Py * wx > 0.0 ? 1.0 : -1.0;
-    const double lx = (Px * L - sg * (Py * R)) / dist2;
-    const double ly = (sg * (Px * R) + Py * L) / dist2;
+    const double id = 1.0 / dist2;
+    const double lx = div_recip(Px * L - sg * (Py * R), dist2, id);
+    const double ly = div_recip(sg * (Px * R) + Py * L, dist2, id);
     nx = -sg * ly;
     ny = sg * lx;
     const double sdot = Vx * lx + Vy * ly;
