@@ -7,7 +7,9 @@ and the per-scene max speed and time horizon.  Memory is bounded by step
 checkpointing: the forward keeps the state every ``sim.segment`` steps; the
 backward replays each segment from its checkpoint with the steps recorded
 (neighbour ids, half-plane choices and active constraints), then runs the
-hand-written adjoint of each step in reverse (orca_backward).
+hand-written adjoint of each step in reverse (orca_backward).  The forward
+records its last segment as it goes, so the backward replays that one only
+if the context has stepped since (a recorded step is bitwise the plain one).
 """
 from __future__ import annotations
 
@@ -59,11 +61,13 @@ class OrcaTrajectory(torch.autograd.Function):
         while done < spec.n_steps:
             k = min(spec.segment, spec.n_steps - done)
             checkpoints.append((pos.clone(), vel.clone(), k))
-            lib.step(spec.offsets, params, pos, vel, pref_c, n_steps=k)
+            last = done + k == spec.n_steps
+            lib.step(spec.offsets, params, pos, vel, pref_c, n_steps=k, save_tape=last)
             done += k
         ctx.spec = spec
         ctx.params = params
         ctx.checkpoints = checkpoints
+        ctx.tape_epoch = lib.step_epoch  # the recording of the last segment
         ctx.save_for_backward(pref_c)
         return pos, vel
 
@@ -78,10 +82,11 @@ class OrcaTrajectory(torch.autograd.Function):
         g_pref = torch.zeros_like(pref_c)
         g_vmax = torch.zeros(n_sc, dtype=torch.float32, device=pref_c.device)
         g_tau = torch.zeros(n_sc, dtype=torch.float32, device=pref_c.device)
-        for pos_c, vel_c, k in reversed(ctx.checkpoints):
-            pos = pos_c.clone()
-            vel = vel_c.clone()
-            lib.step(spec.offsets, params, pos, vel, pref_c, n_steps=k, save_tape=True)
+        for s, (pos_c, vel_c, k) in enumerate(reversed(ctx.checkpoints)):
+            if not (s == 0 and lib.step_epoch == ctx.tape_epoch):
+                pos = pos_c.clone()
+                vel = vel_c.clone()
+                lib.step(spec.offsets, params, pos, vel, pref_c, n_steps=k, save_tape=True)
             for t in reversed(range(k)):
                 lib.backward(t, gp, gv, gp, gv, g_pref, g_vmax, g_tau)
         return gp, gv, g_pref, g_vmax, g_tau, None

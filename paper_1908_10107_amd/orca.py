@@ -138,6 +138,9 @@ class Context:
         self.h = h
         self.max_agents = max_agents
         self._scenes = None
+        # counts orca_step calls: a recording is still the last thing the
+        # context did while this has not moved on
+        self.step_epoch = 0
 
     # ----------------------------------------------------------- plumbing
     def _check(self, rc):
@@ -187,6 +190,7 @@ class Context:
     def step(self, offsets, params, pos, vel, pref_vel, goals=None, n_steps=1, save_tape=False):
         ns, offs, pa, n = self._scene_args(offsets, params)
         self._sync_stream()
+        self.step_epoch += 1
         self._check(self.lib.orca_step(self.h, ns, offs.ctypes.data_as(_P), pa,
                                        _dev_ptr(pos, "pos", n), _dev_ptr(vel, "vel", n),
                                        _dev_ptr(pref_vel, "pref_vel", n),

@@ -130,3 +130,36 @@ def test_trajectory_gradient_200_steps():
         say("  direction %-6s: adjoint %.8g  forward mode %.8g  (loss %.6f)" % (name, mine, dL, L))
         assert abs(mine - dL) <= 1e-3 * max(abs(dL), 1e-6 * abs(L)), (name, mine, dL)
     spec.ctx.close()
+
+
+def test_trajectory_gradient_with_and_without_the_kept_recording():
+    """The forward records its last segment; the backward uses that recording
+    only if the context has not stepped since.  With another step in between
+    it replays the segment, and the gradients agree (up to the order of the
+    float64 atomic sums of the adjoint's scatter)."""
+    torch = _torch()
+    from paper_1908_10107_amd import autograd, orca
+    say("case trajectory gradient: kept recording vs replay")
+    w = scenes.grad(n=1024)
+    d = orca.to_device(w)
+    p = w.params[0]
+    y = torch.from_numpy(w.targets).cuda()
+    grads = []
+    for disturb in (False, True):
+        pref = d["pref_vel"].clone().requires_grad_(True)
+        vmax = torch.tensor([p.max_speed], device="cuda", requires_grad=True)
+        tau = torch.tensor([p.time_horizon], device="cuda", requires_grad=True)
+        spec = autograd.TrajectorySpec(offsets=list(w.offsets), params=list(w.params),
+                                       n_steps=50, segment=20)
+        pos, vel = autograd.trajectory(d["pos"], d["vel"], pref, vmax, tau, spec)
+        if disturb:
+            # an unrelated recorded step on the same context overwrites the tape
+            q, v = d["pos"].clone(), d["vel"].clone()
+            spec.ctx.step(w.offsets, w.params, q, v, d["pref_vel"], n_steps=3, save_tape=True)
+        ((pos.double() - y.double()) ** 2).sum().backward()
+        torch.cuda.synchronize()
+        grads.append((pref.grad.cpu().numpy(), vmax.grad.cpu().numpy(), tau.grad.cpu().numpy()))
+        spec.ctx.close()
+    for a, b in zip(*grads):
+        assert np.allclose(a, b, rtol=1e-5, atol=1e-6 * np.abs(a).max())
+    assert np.abs(grads[0][0]).max() > 0
