@@ -2,17 +2,19 @@
 //
 // The step is x' = x + dt v', v_next = v', with v' the velocity choice of
 // section 3 made from the state at the step's start.  Given dL/dx' and
-// dL/dv_next, k_backward handles each agent i:
+// dL/dv_next, k_backward handles each agent i (in the recorded step's cell
+// order, so a wave's neighbours and atomics are close together):
 //   g = dL/dv'_i = dL/dv_next_i + dt dL/dx'_i;
 //   refetch from the tape the (at most five) half-planes that fix v'_i
 //   (orca_adjoint.h), push g back through the programs to those half-planes,
 //   to vhat_i and to v_max, then through each half-plane to its relative
 //   position P = x_j - x_i, relative velocity V = v_i - v_j, v_i (through
 //   v_i + u/2) and tau;
-//   scatter P and V gradients to agents i and j with float64 atomics.
+//   scatter P and V gradients to agents i and j with float64 atomics into
+//   accumulators indexed by the step's sorted index.
 // k_backward_finish then writes dL/dx = dL/dx' + (scattered part), dL/dv
-// (scattered part), adds the per-scene v_max and tau gradients, and clears
-// the float64 accumulators for the next use.
+// (scattered part) by agent id, adds the per-scene v_max and tau gradients,
+// and clears the float64 accumulators for the next use.
 #include <hip/hip_runtime.h>
 
 #include "orca_internal.h"
@@ -27,16 +29,17 @@ __device__ __forceinline__ double wave_sum_f64(double v)
 
 __global__ __launch_bounds__(256) void k_backward(BackArgs a)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;  // sorted index
     const int32_t n = a.n;
-    const bool live = i < n;
+    const bool live = s < n;
     int32_t sc = 0;
     double gvmax = 0.0, gtau = 0.0;
     if (live) {
+        const int32_t i = a.sid[s];
         sc = a.agent_scene[i];
         const SceneDev p = a.sp[sc];
-        const TapeCode tc = a.codes[i];
-        const float4 me = a.state[i];
+        const TapeCode tc = a.codes[s];
+        const float4 me = a.state[s];
         const double tau = (double)p.tau, dt = (double)p.dt;
         const double ri = (double)(a.radius ? a.radius[i] : p.radius);
         const double vmax = (double)(a.max_speed ? a.max_speed[i] : p.vmax);
@@ -55,14 +58,17 @@ __global__ __launch_bounds__(256) void k_backward(BackArgs a)
             rows[q] = RowGeom{};
             Rq[q] = 0.0;
             if (r[q] >= 0) {
-                const int32_t j = a.nbr[(int64_t)i * a.krow + r[q]];
+                // sorted index of the neighbour; bit 31: agent i does not come
+                // first of the pair
+                const int32_t entry = a.nbr[(int64_t)r[q] * a.ld + s];
+                const int32_t j = entry & 0x7fffffff;
                 const float4 o = a.state[j];
                 rows[q].Px = (double)o.x - (double)me.x;
                 rows[q].Py = (double)o.y - (double)me.y;
                 rows[q].Vx = vix - (double)o.z;
                 rows[q].Vy = viy - (double)o.w;
-                rows[q].first = i < j;
-                Rq[q] = ri + (double)(a.radius ? a.radius[j] : p.radius);
+                rows[q].first = entry >= 0;
+                Rq[q] = ri + (double)(a.radius ? a.radius[a.sid[j]] : p.radius);
                 row_geom(rows[q], Rq[q], tau, dt, vix, viy);
                 js[q] = j;
             }
@@ -71,7 +77,9 @@ __global__ __launch_bounds__(256) void k_backward(BackArgs a)
         sg.clear();
         double gvhx = 0.0, gvhy = 0.0;
         choice_vjp(rows, tc, vmax, vhx, vhy, gx, gy, sg, gvhx, gvhy, gvmax);
-        double gvix = 0.0, gviy = 0.0;
+        // agent i's own share is summed over its slots first: four atomics
+        // per neighbour and four for i
+        double gvix = 0.0, gviy = 0.0, gxi = 0.0, gyi = 0.0;
 #pragma unroll
         for (int q = 0; q < kSlots; ++q) {
             if (js[q] < 0) continue;
@@ -82,15 +90,17 @@ __global__ __launch_bounds__(256) void k_backward(BackArgs a)
             // P = x_j - x_i, V = v_i - v_j
             atomicAdd(&a.acc[j], gPx);
             atomicAdd(&a.acc[n + j], gPy);
-            atomicAdd(&a.acc[i], -gPx);
-            atomicAdd(&a.acc[n + i], -gPy);
             atomicAdd(&a.acc[2 * n + j], -gVx);
             atomicAdd(&a.acc[3 * n + j], -gVy);
+            gxi -= gPx;
+            gyi -= gPy;
             gvix += gVx;
             gviy += gVy;
         }
-        atomicAdd(&a.acc[2 * n + i], gvix);
-        atomicAdd(&a.acc[3 * n + i], gviy);
+        atomicAdd(&a.acc[s], gxi);
+        atomicAdd(&a.acc[n + s], gyi);
+        atomicAdd(&a.acc[2 * n + s], gvix);
+        atomicAdd(&a.acc[3 * n + s], gviy);
         a.g_pref[i] += (float)gvhx;
         a.g_pref[n + i] += (float)gvhy;
         if (a.max_speed) gvmax = 0.0;  // the agent's own max speed is a constant here
@@ -112,25 +122,26 @@ __global__ __launch_bounds__(256) void k_backward(BackArgs a)
 
 __global__ __launch_bounds__(256) void k_backward_finish(BackArgs a)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;  // sorted index
     const int32_t n = a.n;
-    if (i < n) {
-        const double gx = (double)a.g_pos_next[i] + a.acc[i];
-        const double gy = (double)a.g_pos_next[n + i] + a.acc[n + i];
+    if (s < n) {
+        const int32_t i = a.sid[s];
+        const double gx = (double)a.g_pos_next[i] + a.acc[s];
+        const double gy = (double)a.g_pos_next[n + i] + a.acc[n + s];
         a.g_pos[i] = (float)gx;
         a.g_pos[n + i] = (float)gy;
-        a.g_vel[i] = (float)a.acc[2 * n + i];
-        a.g_vel[n + i] = (float)a.acc[3 * n + i];
-        a.acc[i] = 0.0;
-        a.acc[n + i] = 0.0;
-        a.acc[2 * n + i] = 0.0;
-        a.acc[3 * n + i] = 0.0;
+        a.g_vel[i] = (float)a.acc[2 * n + s];
+        a.g_vel[n + i] = (float)a.acc[3 * n + s];
+        a.acc[s] = 0.0;
+        a.acc[n + s] = 0.0;
+        a.acc[2 * n + s] = 0.0;
+        a.acc[3 * n + s] = 0.0;
     }
-    if (i < a.n_scenes) {
-        if (a.g_max_speed) a.g_max_speed[i] += (float)a.acc_scene[i];
-        if (a.g_time_horizon) a.g_time_horizon[i] += (float)a.acc_scene[a.n_scenes + i];
-        a.acc_scene[i] = 0.0;
-        a.acc_scene[a.n_scenes + i] = 0.0;
+    if (s < a.n_scenes) {  // per-scene parameters, scene s
+        if (a.g_max_speed) a.g_max_speed[s] += (float)a.acc_scene[s];
+        if (a.g_time_horizon) a.g_time_horizon[s] += (float)a.acc_scene[a.n_scenes + s];
+        a.acc_scene[s] = 0.0;
+        a.acc_scene[a.n_scenes + s] = 0.0;
     }
 }
 

@@ -81,9 +81,13 @@ struct orca_ctx {
     int64_t prof_steps = 0, prof_fallback = 0;
 
     // tape of recorded steps for orca_backward
+    // each recorded step in its own cell order (sorted index s): the state,
+    // the neighbour lists as the neighbour kernel wrote them ([k_max, A]) and
+    // the id of each s (the counting sort writes these two in place)
     float4 *tape_state = nullptr;           // [tape_steps, A]
-    int32_t *tape_nbr = nullptr;            // [tape_steps, A, k_max]
+    int32_t *tape_nbr = nullptr;            // [tape_steps, k_max, A]
     orca::TapeCode *tape_codes = nullptr;   // [tape_steps, A]
+    int32_t *tape_sid = nullptr;            // [tape_steps, A]
     double *acc = nullptr;                  // [4, A]
     double *acc_scene = nullptr;            // [2, S]
     int32_t tape_len = 0;                   // steps held by the last recording
@@ -408,7 +412,8 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
     if (ok && T > 0)
         ok = alloc((void **)&ctx->tape_state, sizeof(float4) * T * A) &&
              alloc((void **)&ctx->tape_nbr, sizeof(int32_t) * T * A * (size_t)k_max) &&
-             alloc((void **)&ctx->tape_codes, sizeof(orca::TapeCode) * T * A);
+             alloc((void **)&ctx->tape_codes, sizeof(orca::TapeCode) * T * A) &&
+             alloc((void **)&ctx->tape_sid, sizeof(int32_t) * T * A);
     if (!ok) {
         free_all(ctx);
         delete ctx;
@@ -568,11 +573,13 @@ int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
     if (save_tape) ctx->tape_len = 0;
     for (int32_t t = 0; t < n_steps; ++t) {
         if (save_tape) {
+            // the step's neighbour lists and cell-order ids go straight to
+            // the tape slot; state and choices are written by sorted index
             const size_t A = (size_t)ctx->max_agents;
             pl.out.tape_state = ctx->tape_state + (size_t)t * A;
             pl.out.tape_codes = ctx->tape_codes + (size_t)t * A;
-            pl.out.nbr_out = ctx->tape_nbr + (size_t)t * A * (size_t)ctx->k_max;
-            pl.out.krow = ctx->k_max;
+            pl.nbr = ctx->tape_nbr + (size_t)t * A * (size_t)ctx->k_max;
+            pl.sid = ctx->tape_sid + (size_t)t * A;
         }
         rc = run_pass(ctx, pl, pos, vel);
         if (rc != ORCA_OK) return rc;
@@ -738,12 +745,13 @@ int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
     orca::BackArgs a{};
     a.n = (int32_t)ctx->n;
     a.n_scenes = ctx->n_scenes;
-    a.krow = ctx->k_max;
+    a.ld = (int32_t)A;
     a.agent_scene = ctx->agent_scene;
     a.sp = ctx->sp;
     a.state = ctx->tape_state + (size_t)tape_step * A;
     a.nbr = ctx->tape_nbr + (size_t)tape_step * A * (size_t)ctx->k_max;
     a.codes = ctx->tape_codes + (size_t)tape_step * A;
+    a.sid = ctx->tape_sid + (size_t)tape_step * A;
     a.pref = ctx->tape_pref;
     a.g_pos_next = g_pos_next;
     a.g_vel_next = g_vel_next;

@@ -125,8 +125,9 @@ struct OutArgs {
     uint8_t *status;     // [N] or nullptr
     int32_t *nbr_out;    // [N, krow] or nullptr
     int32_t krow;
-    float4 *tape_state;  // recorded step: state (x, y, vx, vy) at the step's start, or nullptr
-    TapeCode *tape_codes;  // recorded step: how each velocity was chosen
+    float4 *tape_state;  // recorded step: state (x, y, vx, vy) at the step's start by sorted
+                         // index, or nullptr
+    TapeCode *tape_codes;  // recorded step: how each velocity was chosen, by sorted index
     AgentProps ag;         // per-agent properties of this pass
     LifeArgs life;         // spawning and removal (life.spawn_step == nullptr: off)
 };
@@ -171,19 +172,21 @@ hipError_t launch_lp(const Plan &pl, int kmax, hipStream_t st);
 hipError_t launch_fallback(const Plan &pl, int kmax, hipStream_t st);
 
 // Adjoint of one recorded step (orca_adjoint.hip).
+// The tape of a step is in that step's cell order (sorted index s).
 struct BackArgs {
-    int32_t n, n_scenes, krow;
+    int32_t n, n_scenes, ld;
     const int32_t *agent_scene;
     const SceneDev *sp;
-    const float4 *state;      // tape: state at the step's start
-    const int32_t *nbr;       // tape: neighbour ids [n, krow]
-    const TapeCode *codes;    // tape: choices
+    const float4 *state;      // tape: state at the step's start [s]
+    const int32_t *nbr;       // tape: neighbour lists [k * ld + s] as k_knn wrote them
+    const TapeCode *codes;    // tape: choices [s]
+    const int32_t *sid;       // tape: agent id of each sorted index [s]
     const float *pref;        // fixed preferred velocities [2, n]
     const float *g_pos_next, *g_vel_next;
     float *g_pos, *g_vel, *g_pref, *g_max_speed, *g_time_horizon;
     const float *radius;      // per-agent radii of the recorded step, or nullptr
     const float *max_speed;   // per-agent max speeds of the recorded step, or nullptr
-    double *acc;              // [4, n] float64 accumulators (kept zero between uses)
+    double *acc;              // [4, n] float64 accumulators by sorted index (kept zero)
     double *acc_scene;        // [2, n_scenes]
 };
 hipError_t launch_backward(const BackArgs &a, hipStream_t st);

@@ -780,7 +780,7 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
                                               ncount, out.nbr_out, out.krow);
         Active act;
         const int fail = rows.project(m, vmax, vhx, vhy, vx, vy, &act);
-        if (REC) out.tape_state[id] = me;
+        if (REC) out.tape_state[s] = me;
         if (fail < 0) {
             write_result<LIFE>(out, me.x, me.y, p.dt, id, n, vx, vy, vhx, vhy, 0);
             if (REC) {
@@ -791,7 +791,7 @@ __global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sort
                 tc.d_plane = -1;
                 tc.d_line = (int8_t)kLineNone;
                 tc.d_src = (int8_t)kSrcDisc;
-                out.tape_codes[id] = tc;
+                out.tape_codes[s] = tc;
             }
         } else {
             need_fb = true;
@@ -998,7 +998,7 @@ __device__ __forceinline__ void fallback_items(RS &rows, const OutArgs &out, int
             tc.d_src = (int8_t)stash_row(dact.src, it);
             tc.relaxed_empty = ok ? 0 : 1;
             tc.dstar = d;
-            out.tape_codes[it.id] = tc;
+            out.tape_codes[it.s] = tc;
         }
         write_result<MODE == kModeLife>(out, it.mex, it.mey, it.dt, it.id, n, vx, vy, it.vhx,
                                         it.vhy, 1);
