@@ -104,6 +104,17 @@ def _agents(radius=None, max_speed=None, pref_speed=None, present=None):
     return ctypes.byref(OracleAgents(*[_ptr(a) for a in arrs])), arrs
 
 
+def _offsets(offsets, n, n_scenes):
+    """Scene offsets as int64, checked against the agent count: the C code
+    trusts them for every array bound."""
+    off = np.ascontiguousarray(offsets, np.int64)
+    if off.ndim != 1 or off.size != n_scenes + 1 or off[0] != 0 or off[-1] != n or \
+            np.any(np.diff(off) < 0):
+        raise ValueError("scene offsets %s do not split %d agents into %d scenes"
+                         % (off.tolist()[:8], n, n_scenes))
+    return off
+
+
 def params_array(params):
     arr = (OracleParams * len(params))()
     for s, p in enumerate(params):
@@ -208,7 +219,7 @@ def velocities(pos, vel, pref, offsets, params, goals=None, agents=None, neighbo
     pos, vel, pref, goals = map(_f32, (pos, vel, pref, goals))
     props, keep = _agents(radius, max_speed, pref_speed, present)
     n = pos.shape[1]
-    offsets = np.ascontiguousarray(offsets, np.int64)
+    offsets = _offsets(offsets, n, len(params))
     pa = params_array(params)
     if agents is None:
         m = n
@@ -238,7 +249,7 @@ def step(pos, vel, pref, offsets, params, goals=None, n_steps=1, radius=None, ma
     n = pos.shape[1]
     st = np.zeros(n, np.uint8)
     lib().oracle_step(n, _ptr(pos), _ptr(vel), _ptr(pref), _ptr(goals), ag,
-                      len(params), _ptr(np.ascontiguousarray(offsets, np.int64)),
+                      len(params), _ptr(_offsets(offsets, n, len(params))),
                       params_array(params), int(n_steps), _ptr(st))
     return pos, vel, pref, st
 
@@ -264,7 +275,7 @@ def life_step(pos, vel, pref, offsets, params, goals, spawn_step, state, t0, n_s
         L.oracle_life_step.restype = None
         L._life_ready = True
     L.oracle_life_step(n, _ptr(pos), _ptr(vel), _ptr(pref), _ptr(goals), ag, len(params),
-                       _ptr(np.ascontiguousarray(offsets, np.int64)), params_array(params),
+                       _ptr(_offsets(offsets, n, len(params))), params_array(params),
                        int(n_steps), _ptr(spawn), _ptr(state), int(t0), _ptr(st))
     return pos, vel, pref, state, st
 
@@ -301,7 +312,7 @@ def traj_loss(pos0, vel0, pref, offsets, params, vmax, tau, n_steps, targets, ra
     ag, keep = _agents(radius, max_speed, None)
     n = pos0.shape[1]
     return _grad_lib().oracle_traj_loss(n, _ptr(pos0), _ptr(vel0), _ptr(pref), len(params),
-                                        _ptr(np.ascontiguousarray(offsets, np.int64)),
+                                        _ptr(_offsets(offsets, n, len(params))),
                                         params_array(params), _ptr(vmax), _ptr(tau), int(n_steps),
                                         _ptr(targets), ag)
 
@@ -318,7 +329,7 @@ def traj_jvp(pos0, vel0, pref, offsets, params, vmax, tau, n_steps, targets, dpr
     n = pos0.shape[1]
     L, dL = ctypes.c_double(), ctypes.c_double()
     _grad_lib().oracle_traj_jvp(n, _ptr(pos0), _ptr(vel0), _ptr(pref), len(params),
-                                _ptr(np.ascontiguousarray(offsets, np.int64)),
+                                _ptr(_offsets(offsets, n, len(params))),
                                 params_array(params), _ptr(vmax), _ptr(tau), int(n_steps),
                                 _ptr(targets), _ptr(dpref), _ptr(dvmax), _ptr(dtau),
                                 int(bool(f32_state)), ag, ctypes.byref(L), ctypes.byref(dL))
@@ -335,7 +346,7 @@ def step_jvp(pos, vel, pref, offsets, params, dpos, dvel, dpref, dvmax, dtau, ra
     op = np.zeros((2, n))
     ov = np.zeros((2, n))
     _grad_lib().oracle_step_jvp(n, _ptr(pos), _ptr(vel), _ptr(pref), len(params),
-                                _ptr(np.ascontiguousarray(offsets, np.int64)),
+                                _ptr(_offsets(offsets, n, len(params))),
                                 params_array(params), _ptr(dpos), _ptr(dvel), _ptr(dpref),
                                 _ptr(dvmax), _ptr(dtau), ag, _ptr(op), _ptr(ov))
     return op, ov

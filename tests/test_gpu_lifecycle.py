@@ -278,3 +278,71 @@ def test_crossing_lanes_and_turning_on_the_gpu():
     say("  turning speed %.3f .. %.3f m/s over %d samples" % (min(lz), max(lz), len(lz)))
     assert len(lz) >= 8 and min(lz) > 0.25
     ctx.close()
+
+
+def concat_scenes(ws):
+    """Back-to-back scenes of several workloads (each one scene) as one workload."""
+    pos = np.concatenate([w.pos for w in ws], axis=1)
+    goals = np.concatenate([w.goals for w in ws], axis=1)
+    n = pos.shape[1]
+    offs = np.zeros(len(ws) + 1, np.int64)
+    offs[1:] = np.cumsum([w.pos.shape[1] for w in ws])
+    params = [w.params[0] for w in ws]
+    out = scenes.Workload("multi", np.ascontiguousarray(pos), np.zeros((2, n), np.float32),
+                          np.ascontiguousarray(goals), np.zeros((2, n), np.float32), offs,
+                          params, 0)
+    out.spawn_step = np.concatenate([w.spawn_step for w in ws]).astype(np.int32)
+    return out
+
+
+def test_life_steps_with_several_scenes():
+    """Three scenes with their own parameters (one empty) share the cell of
+    absent agents: every step from the GPU's state matches the reference."""
+    torch = _torch()
+    say("case life several scenes")
+    a = small_crossing(2, False)
+    b = scenes.crossing_spawn(ways=8, n=240, spawn_steps=150, ring=10.0, region=6.0,
+                              neighbor_dist=4.0, max_neighbors=7, time_horizon=3.0)
+    e = scenes.crossing_spawn(ways=2, n=2, spawn_steps=1)
+    e.pos, e.goals, e.spawn_step = e.pos[:, :0], e.goals[:, :0], e.spawn_step[:0]
+    w = concat_scenes([a, e, b])
+    assert list(np.diff(w.offsets)) == [a.n, 0, b.n] and w.n == a.n + b.n
+    ctx, d = setup(w, torch)
+    dt = np.array([np.float32(p.dt) for p in w.params], np.float64)
+    scene = np.repeat(np.arange(3), np.diff(w.offsets))
+    arrivals = 0
+    for t in range(400):
+        check = t % 4 == 0 or t >= 250
+        if check:
+            pos0 = d["pos"].cpu().numpy()
+            vel0 = d["vel"].cpu().numpy()
+            pref0 = d["pref_vel"].cpu().numpy()
+            state0 = d["state"].cpu().numpy()
+        ctx.step(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], goals=d["goals"])
+        if not check:
+            continue
+        p1, v1 = d["pos"].cpu().numpy(), d["vel"].cpu().numpy()
+        s1 = d["state"].cpu().numpy()
+        po, vo, _, so, st = oracle.life_step(pos0, vel0, pref0, w.offsets, w.params, w.goals,
+                                             w.spawn_step, state0, t, n_steps=1)
+        present = (w.spawn_step <= t) & (state0 == 0)
+        assert np.array_equal(p1[:, ~present], pos0[:, ~present]), t
+        if present.any():
+            err = np.abs(v1[:, present].astype(np.float64) - vo[:, present]).max()
+            assert err < TOL_V, (t, err)
+            want = pos0[:, present].astype(np.float64) + dt[scene[present]] * \
+                vo[:, present].astype(np.float64)
+            perr = np.abs(p1[:, present] - want) - (dt[scene[present]] * TOL_V + np.spacing(
+                np.abs(want).astype(np.float32)))
+            assert perr.max() <= 0, t
+        dist = np.hypot(*(w.goals.astype(np.float64) - po.astype(np.float64)))
+        near = np.abs(dist - w.params[0].radius) < TOL_ARRIVE
+        assert not ((s1 != so) & ~near).any(), t
+        if (s1 != so).any():
+            d["state"].copy_(torch.from_numpy(so).cuda())
+            ctx.set_lifecycle(d["spawn_step"], d["state"], t + 1)
+        arrivals += int(((s1 == 1) & (state0 == 0)).sum())
+        assert ctx.population()[1] == int(present.sum())
+    say("  arrivals %d" % arrivals)
+    assert arrivals >= 10
+    ctx.close()

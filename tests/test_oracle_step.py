@@ -141,3 +141,15 @@ def test_two_way_crossing_with_paper_parameters(oracle_lib):
                                                       w.params, goals=w.goals)
     # the crowds made progress toward their goals
     assert np.linalg.norm(w.goals - w.pos, axis=0).mean() < np.linalg.norm(goals - pos, axis=0).mean() - 3.0
+
+
+def test_scene_offsets_are_checked_against_the_agents(oracle_lib):
+    # the C reference trusts the offsets for every array bound, so the binding
+    # refuses offsets that do not split the agents into the scenes
+    w = scenes.tiny_random(50, 10.0, seed=3)
+    for bad in ([0, 52], [0, 30, 25, 50], [1, 50], [0, 50, 50]):
+        with pytest.raises(ValueError):
+            oracle_lib.velocities(w.pos, w.vel, w.pref_vel, np.array(bad), w.params)
+    with pytest.raises(ValueError):
+        oracle_lib.step(w.pos, w.vel, w.pref_vel, [0, 49], w.params)
+    oracle_lib.velocities(w.pos, w.vel, w.pref_vel, [0, 50], w.params)
