@@ -77,12 +77,17 @@ ORCA_HD inline void obstacle_exit(double Px, double Py, double Vx, double Vy, do
     const double wx = Vx - div_recip(Px, tc, ic), wy = Vy - div_recip(Py, tc, ic);
     const double w2 = wx * wx + wy * wy;
     const double wP = wx * Px + wy * Py;
-    if (!apart || (wP < 0.0 && wP * wP > R2 * w2)) {
-        const double wl = sqrt(w2);
+    const bool circle = !apart || (wP < 0.0 && wP * wP > R2 * w2);
+    // Each case takes one square root and one reciprocal: |w| and 1/|w| on
+    // the circle, the leg length L and 1/|P|^2 on a leg.  Selecting their
+    // arguments first lets a wave with lanes in both cases run them once.
+    const double root = sqrt(circle ? w2 : dist2 - R2);
+    const double rec = 1.0 / (circle ? root : dist2);
+    if (circle) {
+        const double wl = root;
         if (wl > 0.0) {
-            const double iw = 1.0 / wl;
-            nx = div_recip(wx, wl, iw);
-            ny = div_recip(wy, wl, iw);
+            nx = div_recip(wx, wl, rec);
+            ny = div_recip(wy, wl, rec);
         } else if (dist2 > 0.0) {
             // in contact and not moving apart: away from the neighbour
             const double pl = sqrt(dist2);
@@ -98,11 +103,10 @@ ORCA_HD inline void obstacle_exit(double Px, double Py, double Vx, double Vy, do
         return;
     }
     // nearest boundary point on a tangent leg: left (sg = +1) if w is left of P
-    const double L = sqrt(dist2 - R2);
+    const double L = root;
     const double sg = Px * wy - Py * wx > 0.0 ? 1.0 : -1.0;
-    const double id = 1.0 / dist2;
-    const double lx = div_recip(Px * L - sg * (Py * R), dist2, id);
-    const double ly = div_recip(sg * (Px * R) + Py * L, dist2, id);
+    const double lx = div_recip(Px * L - sg * (Py * R), dist2, rec);
+    const double ly = div_recip(sg * (Px * R) + Py * L, dist2, rec);
     nx = -sg * ly;
     ny = sg * lx;
     const double sdot = Vx * lx + Vy * ly;
