@@ -78,16 +78,22 @@ ORCA_HD inline void obstacle_exit(double Px, double Py, double Vx, double Vy, do
     const double w2 = wx * wx + wy * wy;
     const double wP = wx * Px + wy * Py;
     const bool circle = !apart || (wP < 0.0 && wP * wP > R2 * w2);
-    // Each case takes one square root and one reciprocal: |w| and 1/|w| on
-    // the circle, the leg length L and 1/|P|^2 on a leg.  Selecting their
-    // arguments first lets a wave with lanes in both cases run them once.
+    // Each case takes one square root and two quotients by one divisor: |w|
+    // and w / |w| on the circle; the leg length L and the leg direction
+    // (L P -+ R P_perp) / |P|^2 on a leg (left, sg = +1, if w is left of P).
+    // Selecting their arguments first lets a wave with lanes in both cases
+    // run them once.
     const double root = sqrt(circle ? w2 : dist2 - R2);
-    const double rec = 1.0 / (circle ? root : dist2);
+    const double den = circle ? root : dist2;
+    const double rec = 1.0 / den;
+    const double sg = Px * wy - Py * wx > 0.0 ? 1.0 : -1.0;
+    const double q1 = div_recip(circle ? wx : Px * root - sg * (Py * R), den, rec);
+    const double q2 = div_recip(circle ? wy : sg * (Px * R) + Py * root, den, rec);
     if (circle) {
         const double wl = root;
         if (wl > 0.0) {
-            nx = div_recip(wx, wl, rec);
-            ny = div_recip(wy, wl, rec);
+            nx = q1;
+            ny = q2;
         } else if (dist2 > 0.0) {
             // in contact and not moving apart: away from the neighbour
             const double pl = sqrt(dist2);
@@ -102,11 +108,8 @@ ORCA_HD inline void obstacle_exit(double Px, double Py, double Vx, double Vy, do
         uy = f * ny;
         return;
     }
-    // nearest boundary point on a tangent leg: left (sg = +1) if w is left of P
-    const double L = root;
-    const double sg = Px * wy - Py * wx > 0.0 ? 1.0 : -1.0;
-    const double lx = div_recip(Px * L - sg * (Py * R), dist2, rec);
-    const double ly = div_recip(sg * (Px * R) + Py * L, dist2, rec);
+    // nearest boundary point on the tangent leg, direction (lx, ly)
+    const double lx = q1, ly = q2;
     nx = -sg * ly;
     ny = sg * lx;
     const double sdot = Vx * lx + Vy * ly;
