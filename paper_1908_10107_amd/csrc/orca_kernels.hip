@@ -899,9 +899,9 @@ __global__ __launch_bounds__(kFbSortBlock) void k_fb_sort(const uint8_t *__restr
     }
 }
 
-// Rows of k_fallback: up to 16 in registers, read with wave-uniform indices
-// only (every loop of the programs runs over fixed bounds), more in a per-lane
-// LDS column.
+// Rows of k_fallback: up to 16 in registers, read there with wave-uniform
+// indices (every loop of the programs runs over fixed bounds) and from the
+// agent's stash slot with a lane's own index; more in a per-lane LDS column.
 template <int KMAX, bool IN_REGS = (KMAX <= kLpRegRows)>
 struct FbRows;
 template <int KMAX>
@@ -911,8 +911,17 @@ struct FbRows<KMAX, true> {
     double (&nx)[KMAX];
     double (&ny)[KMAX];
     double (&b)[KMAX];
+    const double2 *gn;  // the same rows in the stash slot
+    const double *gb;
     __device__ __forceinline__ double2 N(int k) const { return make_double2(nx[k], ny[k]); }
     __device__ __forceinline__ double B(int k) const { return b[k]; }
+    __device__ __forceinline__ double2 NL(int k) const { return gn[k]; }
+    __device__ __forceinline__ double BL(int k) const { return gb[k]; }
+    __device__ __forceinline__ void slot(const double2 *n_, const double *b_)
+    {
+        gn = n_;
+        gb = b_;
+    }
     __device__ __forceinline__ void set(int k, double2 nk, double bk)
     {
         nx[k] = nk.x;
@@ -925,6 +934,9 @@ struct FbRows<KMAX, false> {
     Lane L;
     __device__ __forceinline__ double2 N(int k) const { return L.N(k); }
     __device__ __forceinline__ double B(int k) const { return L.B(k); }
+    __device__ __forceinline__ double2 NL(int k) const { return L.N(k); }
+    __device__ __forceinline__ double BL(int k) const { return L.B(k); }
+    __device__ __forceinline__ void slot(const double2 *, const double *) {}
     __device__ __forceinline__ void set(int k, double2 nk, double bk)
     {
         L.n[k * kLpStride] = nk;
@@ -946,6 +958,7 @@ __device__ __forceinline__ void fallback_items(RS &rows, const OutArgs &out, int
         const int m = it.m, fail = it.fail;
         const double2 *gn = stash_n + (int64_t)slot * kcap;
         const double *gb = stash_b + (int64_t)slot * kcap;
+        rows.slot(gn, gb);
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             if (k < m) rows.set(k, gn[k], gb[k]);
@@ -1025,7 +1038,7 @@ __global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, i
     const uint32_t count = counters->n_fallback;
     double rnx[kRegs ? KMAX : 1], rny[kRegs ? KMAX : 1], rb[kRegs ? KMAX : 1];
     if constexpr (kRegs) {
-        FbRows<KMAX> rows{rnx, rny, rb};
+        FbRows<KMAX> rows{rnx, rny, rb, nullptr, nullptr};
         fallback_items<KMAX, MODE>(rows, out, n, kcap, fb_list, fb_order, stash_n, stash_b, count);
     } else {
         FbRows<KMAX> rows{Lane{s_n + threadIdx.x, s_b + threadIdx.x}};

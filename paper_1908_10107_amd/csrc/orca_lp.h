@@ -125,6 +125,8 @@ struct Lane {
     double *b;
     ORCA_HD inline double2 N(int k) const { return n[k * kLpStride]; }
     ORCA_HD inline double B(int k) const { return b[k * kLpStride]; }
+    ORCA_HD inline double2 NL(int k) const { return n[k * kLpStride]; }
+    ORCA_HD inline double BL(int k) const { return b[k * kLpStride]; }
 };
 
 // What fixes the final point of an incremental 2D program (kept when a step
@@ -312,11 +314,19 @@ ORCA_HDI inline void disc_clip(double vmax, double vhx, double vhy, double &vx, 
     }
 }
 
-// The fallback's programs below take a row store RS (N(k), B(k)) and a
-// compile-time bound KB on the number of rows.  Every loop counter runs over
-// fixed bounds and is the same for all lanes of a wave (a lane outside its own
-// range just skips the body), so a store that keeps the rows in registers is
-// indexed with a wave-uniform index, and nothing returns early.
+// The fallback's programs below take a row store RS and a compile-time bound
+// KB <= 32 on the number of rows.  N(k), B(k) read row k with an index that is
+// the same on every lane of a wave (every such loop runs over fixed bounds, a
+// lane outside its own range just skips the body, so a store that keeps the
+// rows in registers is indexed statically); NL(k), BL(k) read it with a
+// lane's own index.  Each lane walks its own violated rows in order: a pass
+// finds every lane's next one, then the 1D (or plane) programs of that pass
+// run together whatever rows they are on, so a wave pays for its longest
+// sequence of violated rows, not for every row that any of its lanes violates.
+// A lane's steps and arithmetic are those of the one-row-at-a-time program.
+
+// Rows 0..m-1 as bits.
+ORCA_HDI inline uint32_t rows_below(int m) { return m >= 32 ? ~0u : (1u << m) - 1u; }
 
 // Projected constraint i of the plane-k subproblem: i = -1 is "no negative
 // penetration" (-n_k . v >= -b_k), i >= 0 is "constraint i penetrates no more
@@ -342,9 +352,9 @@ ORCA_HDI inline void plane_row(const RS &L, int i, double2 nk, double bk, double
 // p(s) = c_i m_i / |m_i|^2 + s (-m_i.y, m_i.x); each constraint j on it is
 // multiplied through by |m_i|^2 > 0 so no division is needed until the end.
 // Returns false if the subproblem is empty.  The last line and its bound go
-// to *act (line kLineNone: the start point vmax n_k stands).  k is the same on
-// every lane that calls it together.
-template <class RS>
+// to *act (line kLineNone: the start point vmax n_k stands).  k and the row
+// (nk, bk) are the lane's own.
+template <int KB, class RS>
 ORCA_HDI inline bool lp2_plane(const RS &L, int k, double2 nk, double bk, double vmax, double &vx,
                               double &vy, Active *act)
 {
@@ -354,8 +364,8 @@ ORCA_HDI inline bool lp2_plane(const RS &L, int k, double2 nk, double bk, double
     act->line = kLineNone;
     act->src = kSrcDisc;
     bool ok = true;
-    for (int i = -1; i < k; ++i) {
-        if (!ok) continue;
+    for (int i = -1; i < KB - 1; ++i) {
+        if (!ok || i >= k) continue;
         double mx, my, ci;
         plane_row(L, i, nk, bk, mx, my, ci);
         ORCA_COUNT(plane_check);
@@ -419,20 +429,29 @@ template <int KB, class RS>
 ORCA_HDI inline double lp3_least_penetration(const RS &L, int m, int start, double vmax, double &vx,
                                             double &vy, int *plane, Active *act)
 {
+    static_assert(KB <= 32, "row sets are 32-bit masks");
     double t = 0.0;
     *plane = -1;
     act->line = kLineNone;
     act->src = kSrcDisc;
-    for (int k = 0; k < KB; ++k) {
-        if (k < start || k >= m) continue;
-        const double2 nk = L.N(k);
-        const double bk = L.B(k);
-        ORCA_COUNT(lp3_check);
-        if (nk.x * vx + nk.y * vy + t >= bk) continue;
+    uint32_t left = rows_below(m) & ~rows_below(start);  // rows not yet tested
+#pragma unroll 1
+    for (int pass = 0; pass < KB; ++pass) {
+        // the lane's first untested row that (v, t) violates
+        int k = KB;
+        for (int u = KB - 1; u >= 0; --u) {
+            const double2 nu = L.N(u);
+            const bool hit = ((left >> u) & 1u) != 0u && !(nu.x * vx + nu.y * vy + t >= L.B(u));
+            k = hit ? u : k;
+        }
+        if (k >= KB) break;
+        left &= ~rows_below(k + 1);
         ORCA_COUNT(lp3_plane);
+        const double2 nk = L.NL(k);
+        const double bk = L.BL(k);
         double wx, wy;
         Active pa;
-        if (lp2_plane(L, k, nk, bk, vmax, wx, wy, &pa)) {
+        if (lp2_plane<KB>(L, k, nk, bk, vmax, wx, wy, &pa)) {
             vx = wx;
             vy = wy;
             t = fmax(bk - (nk.x * vx + nk.y * vy), 0.0);
@@ -466,12 +485,11 @@ ORCA_HDI inline int lp2_project_front(const RS &L, int m, const FrontRows &F, do
     act->src = kSrcFree;
     int fail = -1;
     disc_clip(vmax, vhx, vhy, vx, vy);
-    // one step of the incremental projection on row (nk, bk), given the rows
-    // before it: the filled front slots below nf and store rows 0..nrows-1
+    // one step of the incremental projection on the violated row (nk, bk),
+    // given the rows before it: the filled front slots below nf and store rows
+    // 0..nrows-1 (nrows may differ between lanes)
     auto line_step = [&](double2 nk, double bk, int pos, int nf,
                          int nrows) __attribute__((always_inline)) {
-        ORCA_COUNT(lp2_check);
-        if (nk.x * vx + nk.y * vy >= bk) return;
         ORCA_COUNT(lp2_line);
         double h2 = vm2 - bk * bk;
         if (h2 < 0.0) {
@@ -492,7 +510,8 @@ ORCA_HDI inline int lp2_project_front(const RS &L, int m, const FrontRows &F, do
                        (F.b[u] - relax) - bk * (nj.x * nk.x + nj.y * nk.y), F.pos[u]);
             }
         }
-        for (int j = 0; j < nrows; ++j) {
+        for (int j = 0; j < KB - 1; ++j) {
+            if (j >= nrows) continue;
             const double2 nj = L.N(j);
             ORCA_COUNT(lp2_inner);
             iv.add(nj.y * nk.x - nj.x * nk.y, (L.B(j) - relax) - bk * (nj.x * nk.x + nj.y * nk.y),
@@ -510,14 +529,32 @@ ORCA_HDI inline int lp2_project_front(const RS &L, int m, const FrontRows &F, do
         act->line = pos;
         act->src = src;
     };
+    static_assert(KB <= 32, "row sets are 32-bit masks");
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        if (F.pos[u] < 0 || fail >= 0) continue;
+        const double bu = F.b[u] - relax;
+        ORCA_COUNT(lp2_check);
+        if (!(F.n[u].x * vx + F.n[u].y * vy >= bu)) line_step(F.n[u], bu, F.pos[u], u, 0);
+    }
+    // a front row is not taken again: on its own line it would meet itself as
+    // a constraint, with a cross term that rounding leaves nonzero
+    uint32_t left = rows_below(m);
 #pragma unroll
     for (int u = 0; u < 3; ++u)
-        if (F.pos[u] >= 0 && fail < 0) line_step(F.n[u], F.b[u] - relax, F.pos[u], u, 0);
-    for (int k = 0; k < KB; ++k) {
-        // a front row is not taken again: on its own line it would meet itself
-        // as a constraint, with a cross term that rounding leaves nonzero
-        if (k >= m || fail >= 0 || k == F.pos[0] || k == F.pos[1] || k == F.pos[2]) continue;
-        line_step(L.N(k), L.B(k) - relax, k, 3, k);
+        if (F.pos[u] >= 0) left &= ~(1u << F.pos[u]);
+#pragma unroll 1
+    for (int pass = 0; pass < KB && fail < 0; ++pass) {
+        // the lane's first untested row that v violates
+        int k = KB;
+        for (int u = KB - 1; u >= 0; --u) {
+            const double2 nu = L.N(u);
+            const bool hit = ((left >> u) & 1u) != 0u && !(nu.x * vx + nu.y * vy >= L.B(u) - relax);
+            k = hit ? u : k;
+        }
+        if (k >= KB) break;
+        left &= ~rows_below(k + 1);
+        line_step(L.NL(k), L.BL(k) - relax, k, 3, k);
     }
     return fail;
 }
