@@ -598,9 +598,12 @@ struct LpRows<KMAX, false> {
 };
 
 // Load agent s's neighbours and build their half-planes into `rows`.  The
-// neighbour loads are issued eight at a time before those half-planes are
-// built, so one memory latency covers each group.  Neighbour ids are fetched
-// only when they are written out (the pair order comes with the entry).
+// neighbour loads are issued G at a time before those half-planes are built,
+// so one memory latency covers each group: two with the rows in registers,
+// which keeps k_lp within the registers of three waves per SIMD (the other
+// waves then cover the latency), eight with the rows in LDS.  Neighbour ids
+// are fetched only when they are written out (the pair order comes with the
+// entry).
 template <int KMAX, class Rows>
 __device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t id, float4 me,
                                                  const SceneDev &p, const AgentProps &ag,
@@ -610,7 +613,7 @@ __device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t 
                                                  const int32_t *__restrict__ ncount,
                                                  int32_t *__restrict__ nbr_out, int32_t krow)
 {
-    constexpr int G = 8;
+    constexpr int G = KMAX <= kLpRegRows ? 2 : 8;
     const int32_t m = ncount[s];
     // combined radius r_i + r_j (section 4: people of different sizes)
     const double ri = (double)(ag.radius ? ag.radius[id] : p.radius);
@@ -725,23 +728,22 @@ __device__ __forceinline__ void write_result(const OutArgs &o, float mex, float 
 }
 
 // One lane per agent in cell order, half-planes in registers (LDS above 16
-// rows).  Feasible agents finish here; an agent whose projection is empty is
+// rows).  With the rows in registers the kernel is held to the registers of
+// three waves per SIMD: it is bound by the latency of its float64 chains and
+// gathers, which a third wave covers better than the unconstrained two (a few
+// bytes of spill).  Feasible agents finish here; an agent whose projection is
 // handed to the fallback list with everything
 // k_fallback needs (one atomic per wave): its record, its sort key (the failed
 // row) and its half-planes in stash slot `slot`, in stash_position order.
 template <int KMAX, int MODE>
-__global__ __launch_bounds__(kLpBlock) void k_lp(const float4 *__restrict__ sorted,
-                                                 const int32_t *__restrict__ sid,
-                                                 const int32_t *__restrict__ agent_scene,
-                                                 const SceneDev *__restrict__ sp, int32_t n,
-                                                 const int32_t *__restrict__ nbr, int32_t ld,
-                                                 const int32_t *__restrict__ ncount,
-                                                 OutArgs out, FallbackItem *__restrict__ fb_list,
-                                                 uint8_t *__restrict__ fb_key, int32_t kcap,
-                                                 double2 *__restrict__ stash_n,
-                                                 double *__restrict__ stash_b,
-                                                 Counters *__restrict__ counters,
-                                                 const int32_t *__restrict__ cell_start)
+__global__ __launch_bounds__(kLpBlock)
+__attribute__((amdgpu_waves_per_eu(KMAX <= kLpRegRows ? 3 : 1))) void k_lp(
+    const float4 *__restrict__ sorted, const int32_t *__restrict__ sid,
+    const int32_t *__restrict__ agent_scene, const SceneDev *__restrict__ sp, int32_t n,
+    const int32_t *__restrict__ nbr, int32_t ld, const int32_t *__restrict__ ncount, OutArgs out,
+    FallbackItem *__restrict__ fb_list, uint8_t *__restrict__ fb_key, int32_t kcap,
+    double2 *__restrict__ stash_n, double *__restrict__ stash_b, Counters *__restrict__ counters,
+    const int32_t *__restrict__ cell_start)
 {
     constexpr bool REC = MODE == kModeRec, LIFE = MODE == kModeLife;
     constexpr bool kRegs = KMAX <= kLpRegRows;
