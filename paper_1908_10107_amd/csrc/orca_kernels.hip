@@ -439,9 +439,10 @@ __device__ __forceinline__ void knn_run(uint64_t (&best)[KMAX], uint32_t &lim, u
         knn_offer<KMAX>(best, ((uint64_t)hi << 32) | (id + 1u));
         lim = min(nd_lim, (uint32_t)(best[KMAX - 1] >> 32));
     };
-    // candidates kBatch at a time: their positions and ids are loaded
-    // together, so one memory latency covers the batch
-    constexpr int kBatch = KMAX <= 16 ? 4 : 2;
+    // candidates two at a time: their positions and ids are loaded together,
+    // so one memory latency covers the pair (four in flight need the
+    // registers of a sixth wave per SIMD, which hides latency better)
+    constexpr int kBatch = 2;
     for (; i + kBatch <= ie; i += kBatch) {
         float4 o[kBatch];
         uint32_t idb[kBatch];
