@@ -172,7 +172,8 @@ int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
  * Pick the launch shapes for the current workload: threads per neighbour
  * block (64, 128, 256, 512) and persistent fallback waves per compute unit
  * (4, 8, 16, 32, i.e. how many fallback agents each lane takes on), by timing
- * reps velocity passes per candidate with HIP events.  Needs orca_build_grid
+ * velocity passes with HIP events: per candidate one untimed pass, then the
+ * fastest of reps passes for each stage.  Needs orca_build_grid
  * on pos first; writes only new_vel (device [2, N], scratch).  The choice is
  * kept in the context and returned in choice[2] (nullable).  Waits for the
  * stream.
