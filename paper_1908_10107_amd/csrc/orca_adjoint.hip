@@ -27,7 +27,11 @@ __device__ __forceinline__ double wave_sum_f64(double v)
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_backward(BackArgs a)
+// Held to the registers of three waves per SIMD (a few bytes of spill): the
+// kernel waits on its neighbour gathers and float64 chains, which a third
+// wave covers better than the unconstrained two.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_backward(
+    BackArgs a)
 {
     const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;  // sorted index
     const int32_t n = a.n;
