@@ -40,7 +40,7 @@ struct orca_ctx {
     int32_t *key = nullptr, *rank = nullptr, *counts = nullptr, *cell_start = nullptr;
     uint32_t *partial = nullptr;
     float4 *sorted = nullptr;
-    int32_t *sid = nullptr, *skey = nullptr, *inv = nullptr;
+    int32_t *sid = nullptr, *inv = nullptr;
     int32_t *nbr = nullptr, *ncount = nullptr;
     orca::FallbackItem *fb_list = nullptr;
     uint8_t *fb_key = nullptr;
@@ -251,7 +251,6 @@ orca::Plan make_plan(const orca_ctx *ctx)
     p.partial = ctx->partial;
     p.sorted = ctx->sorted;
     p.sid = ctx->sid;
-    p.skey = ctx->skey;
     p.inv = ctx->inv;
     p.nbr = ctx->nbr;
     p.ncount = ctx->ncount;
@@ -397,7 +396,6 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->partial, sizeof(uint32_t) * (size_t)ctx->n_tiles) &&
               alloc((void **)&ctx->sorted, sizeof(float4) * A) &&
               alloc((void **)&ctx->sid, sizeof(int32_t) * A) &&
-              alloc((void **)&ctx->skey, sizeof(int32_t) * A) &&
               alloc((void **)&ctx->inv, sizeof(int32_t) * A) &&
               alloc((void **)&ctx->nbr, sizeof(int32_t) * A * (size_t)k_max) &&
               alloc((void **)&ctx->ncount, sizeof(int32_t) * A) &&

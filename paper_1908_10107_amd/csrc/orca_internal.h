@@ -148,7 +148,7 @@ struct Plan {
     int32_t *key, *rank, *counts, *cell_start;
     uint32_t *partial;
     float4 *sorted;
-    int32_t *sid, *skey, *inv;
+    int32_t *sid, *inv;
     int32_t *nbr, *ncount;
     int32_t kcap;      // rows per stash slot (the context's k_max)
     FallbackItem *fb_list;

@@ -227,6 +227,19 @@ __global__ __launch_bounds__(256) void k_grid(int32_t n_scenes, const int32_t *_
     }
 }
 
+// Cell (cx, cy) of a position in a scene's grid, clamped to the grid.  k_key
+// and k_knn both take it from the agent's float32 coordinates, so they agree.
+__device__ __forceinline__ void cell_of(const GridDev &g, float x, float y, int32_t &cx,
+                                        int32_t &cy)
+{
+    double fx = floor(((double)x - g.x0) / g.cell);
+    double fy = floor(((double)y - g.y0) / g.cell);
+    fx = fmin(fmax(fx, 0.0), (double)(g.nx - 1));
+    fy = fmin(fmax(fy, 0.0), (double)(g.ny - 1));
+    cx = (int32_t)fx;
+    cy = (int32_t)fy;
+}
+
 // Cell key of every agent; an absent agent (not yet spawned at the step
 // counters->step, or removed) goes to the last cell, so it sorts after every
 // present agent and no cell of a scene holds it.  That cell can hold most of
@@ -263,11 +276,9 @@ __global__ __launch_bounds__(256) void k_key(const float *__restrict__ pos, int3
     }
     if (!valid || absent) return;
     const GridDev g = grid[agent_scene[i]];
-    double fx = floor(((double)pos[i] - g.x0) / g.cell);
-    double fy = floor(((double)pos[n + i] - g.y0) / g.cell);
-    fx = fmin(fmax(fx, 0.0), (double)(g.nx - 1));
-    fy = fmin(fmax(fy, 0.0), (double)(g.ny - 1));
-    const int32_t k = g.base + (int32_t)fy * g.nx + (int32_t)fx;
+    int32_t cx, cy;
+    cell_of(g, pos[i], pos[n + i], cx, cy);
+    const int32_t k = g.base + cy * g.nx + cx;
     key[i] = k;
     rank[i] = atomicAdd(&counts[k], 1);
 }
@@ -371,7 +382,6 @@ __global__ __launch_bounds__(256) void k_scatter(const float *__restrict__ pos,
                                                  const int32_t *__restrict__ cell_start,
                                                  float4 *__restrict__ sorted,
                                                  int32_t *__restrict__ sid,
-                                                 int32_t *__restrict__ skey,
                                                  int32_t *__restrict__ inv,
                                                  const float *__restrict__ radius,
                                                  float *__restrict__ srad)
@@ -388,7 +398,6 @@ __global__ __launch_bounds__(256) void k_scatter(const float *__restrict__ pos,
     r.w = vel ? vel[n + i] : 0.f;
     sorted[d] = r;
     sid[d] = i;
-    skey[d] = k;
     inv[i] = d;
 }
 
@@ -477,7 +486,6 @@ __device__ __forceinline__ void knn_run(uint64_t (&best)[KMAX], uint32_t &lim, u
 template <int KMAX>
 __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
                                              const int32_t *__restrict__ sid,
-                                             const int32_t *__restrict__ skey,
                                              const int32_t *__restrict__ inv,
                                              const int32_t *__restrict__ cell_start,
                                              const GridDev *__restrict__ grid,
@@ -507,8 +515,8 @@ __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
     }
     const uint32_t nd_lim = __float_as_uint(nd2) - 1u;
     uint32_t lim = nd_lim;
-    const int32_t c = skey[s] - g.base;
-    const int32_t cy = c / g.nx, cx = c - cy * g.nx;
+    int32_t cx, cy;  // the agent's cell
+    cell_of(g, me.x, me.y, cx, cy);
     uint64_t best[KMAX];
     const int32_t pad = KMAX - K;  // leading slots that hold the key 0
 #pragma unroll
@@ -1070,7 +1078,7 @@ hipError_t launch_knn_k(const Plan &pl, hipStream_t st)
     const int32_t n = pl.n;
     const int32_t bs = pl.knn_block;
     hipLaunchKernelGGL(k_knn<KMAX>, dim3((n + bs - 1) / bs), dim3(bs), 0, st, pl.sorted, pl.sid,
-                       pl.skey, pl.inv, pl.cell_start, pl.grid, pl.agent_scene, pl.sp, n, pl.nbr, pl.ld,
+                       pl.inv, pl.cell_start, pl.grid, pl.agent_scene, pl.sp, n, pl.nbr, pl.ld,
                        pl.ncount, pl.counters, pl.out.life.spawn_step ? 1 : 0);
     return hipGetLastError();
 }
@@ -1174,7 +1182,7 @@ hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, bool 
                        advance && life.spawn_step ? 1 : 0);
     if (n == 0) return hipGetLastError();
     hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, st, pos, vel, n, pl.key,
-                       pl.rank, pl.cell_start, pl.sorted, pl.sid, pl.skey, pl.inv,
+                       pl.rank, pl.cell_start, pl.sorted, pl.sid, pl.inv,
                        pl.out.ag.radius, pl.out.ag.srad);
     return hipGetLastError();
 }
