@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 # Algorithmic work of each stage.
-#   binning (HBM): bbox 8 + key pass 28 + scatter 60 = 96 B per agent, + 12 B per cell.
-#   neighbours (HBM figure): own row 28 + list 4K + count 4 = 32 + 4K B per agent.
+#   binning (HBM): bbox 8 + key pass 28 + scatter 56 = 92 B per agent, + 12 B per cell.
+#   neighbours (HBM figure): own row 24 + list 4K + count 4 = 28 + 4K B per agent.
 #   half-planes + 2D LP (FP64 ALU): 29.2 K + 15.2 K operations per agent
 #     (half-plane construction; projection and the choice of the fallback's
 #     first plane; 710 at K = 16).
@@ -48,9 +48,9 @@ def stage_roofline(stage: int, ms: float, n: int, k: int, cells: int, n_fallback
     """(bound, achieved, peak, unit) of one stage at its average duration ms."""
     s = ms * 1e-3
     if stage == 0:
-        return "hbm", (96.0 * n + 12.0 * cells) / s / 1e9, HBM_PEAK_GBS, "GB/s"
+        return "hbm", (92.0 * n + 12.0 * cells) / s / 1e9, HBM_PEAK_GBS, "GB/s"
     if stage == 1:
-        return "hbm", (32.0 + 4.0 * k) * n / s / 1e9, HBM_PEAK_GBS, "GB/s"
+        return "hbm", (28.0 + 4.0 * k) * n / s / 1e9, HBM_PEAK_GBS, "GB/s"
     if stage == 2:
         return "alu", (HP_OPS_PER_K + LP2_OPS_PER_K) * k * n / s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
     return "alu", FB_OPS_PER_K * k * n_fallback / s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
