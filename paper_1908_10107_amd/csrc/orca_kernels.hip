@@ -107,13 +107,15 @@ __global__ void k_reset_bbox(uint32_t *__restrict__ bbox, int32_t n_scenes)
 // Bounding box per scene.  Block b reduces chunk b (at most kBboxChunk agents
 // of one scene, listed by the host when the scene set changes) in registers
 // and LDS, then folds it into its scene with four atomics: a 1M-agent scene
-// costs 128 x 4 atomics instead of one set per 256 agents.
-__global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ pos, int32_t n,
+// costs 128 x 4 atomics instead of one set per 256 agents.  Blocks of 1024
+// threads keep more of a chunk's loads in flight than 256 (few chunks, so few
+// blocks).
+__global__ __launch_bounds__(kBboxBlock) void k_bbox(const float *__restrict__ pos, int32_t n,
                                               const int2 *__restrict__ chunks,
                                               const int32_t *__restrict__ off,
                                               uint32_t *__restrict__ bbox)
 {
-    __shared__ uint32_t red[4][4];
+    __shared__ uint32_t red[kBboxBlock / 64][4];
     const int2 ch = chunks[blockIdx.x];  // (scene, first agent)
     const int32_t end = min(ch.y + kBboxChunk, off[ch.x + 1]);
     uint32_t mnx = 0xffffffffu, mny = 0xffffffffu, mxx = 0u, mxy = 0u;
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ pos, int
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int32_t w = 1; w < 4; ++w) {
+        for (int32_t w = 1; w < kBboxBlock / 64; ++w) {
             mnx = min(mnx, red[w][0]);
             mny = min(mny, red[w][1]);
             mxx = max(mxx, red[w][2]);
@@ -1165,7 +1167,7 @@ hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, bool 
     const int32_t n = pl.n;
     const LifeArgs &life = pl.out.life;
     if (n > 0)
-        hipLaunchKernelGGL(k_bbox, dim3(pl.n_chunks), dim3(256), 0, st, pos, n, pl.chunks,
+        hipLaunchKernelGGL(k_bbox, dim3(pl.n_chunks), dim3(kBboxBlock), 0, st, pos, n, pl.chunks,
                            pl.off, pl.bbox);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, pl.n_scenes, pl.off, pl.sp, pl.bbox,
                        pl.grid, pl.counters, pl.max_cells, life.spawn_step ? 1 : 0);
