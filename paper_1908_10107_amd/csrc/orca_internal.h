@@ -8,8 +8,8 @@
 
 namespace orca {
 
-constexpr int kScanItems = 16;
-constexpr int kScanBlock = 256;
+constexpr int kScanItems = 4;                       // cells per thread of a scan block
+constexpr int kScanBlock = 1024;                    // 1024 threads: more loads in flight than 256
 constexpr int kScanTile = kScanItems * kScanBlock;  // cells per scan tile
 constexpr int kLpBlock = 64;                        // one wave per LP block
 constexpr int kBboxChunk = 8192;                    // agents per bounding-box block
@@ -17,7 +17,7 @@ constexpr int kBboxBlock = 1024;                    // threads per bounding-box 
 constexpr double kCellMargin = 1.0 + 1.0 / 1024.0;  // cell side / (neighbor_dist / kCellsPerNd)
 constexpr int kCellsPerNd = 2;                      // grid cells across one neighbor_dist
 constexpr int kFbSortChunk = 4096;                  // fallback slots sorted together
-constexpr int kFbSortBlock = 256;
+constexpr int kFbSortBlock = 1024;                  // threads per fallback-sort block (4 slots each)
 
 // Per-scene parameters as the kernels read them.
 struct SceneDev {
