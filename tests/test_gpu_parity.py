@@ -346,22 +346,107 @@ def test_step_equals_velocity_call_plus_euler():
     ctx.close()
 
 
-def test_full_size_ring():
-    """65,536 agents on the 1,200 m circle, every agent, from t = 0 and after steps."""
-    say("case ring 65536")
-    w = scenes.ring()
-    step_parity(w, 3, label="ring", every=1)
+def deep_parity(w, checks, sample=None, label="", seed=5):
+    """Step the GPU through a workload in the launch path the benchmark times
+    (orca_step with goals, many steps per call) and, at each step index in
+    ``checks``, take the GPU's own state and check from it:
+      - the neighbour lists of the checked agents bit for bit against the
+        oracle's (binning, then the definition's order: distance, then id);
+      - the new velocities (a velocity pass and the step itself) within 1e-4
+        m/s of the oracle's, positions within dt * 1e-4 plus one float32
+        rounding;
+      - the fallback labels, which may differ only where the oracle's least
+        penetration is within 1e-5 m/s of zero.
+    Returns one record per check: (step, max |dv|, label differences)."""
+    torch = _torch()
+    from paper_1908_10107_amd import orca
+    kmax = max(p.max_neighbors for p in w.params)
+    ctx = orca.Context(max_agents=w.n, max_scenes=w.n_scenes, k_max=kmax)
+    d = orca.to_device(w)
+    ctx.set_agents(d["radius"], d["max_speed"], d["pref_speed"])
+    rng = np.random.default_rng(seed)
+    dt = np.array([np.float32(p.dt) for p in w.params], np.float64)
+    scene = np.repeat(np.arange(w.n_scenes), np.diff(w.offsets))
+    nbr = torch.empty((w.n, kmax), dtype=torch.int32, device="cuda")
+    status = torch.empty((w.n,), dtype=torch.uint8, device="cuda")
+    rec = []
+    t = 0
+    for tc in sorted(set(checks)):
+        if tc > t:
+            ctx.step(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], goals=d["goals"],
+                     n_steps=tc - t)
+            t = tc
+        agents = None if sample is None else np.sort(rng.choice(w.n, sample, replace=False))
+        idx = np.arange(w.n) if agents is None else agents
+        tidx = torch.from_numpy(idx).to("cuda")
+        pos0 = d["pos"].cpu().numpy()
+        vel0 = d["vel"].cpu().numpy()
+        pref0 = d["pref_vel"].cpu().numpy()
+        # a velocity pass from this state: neighbour lists, velocities, labels
+        ctx.build_grid(w.offsets, w.params, d["pos"])
+        nv = ctx.compute_velocities(d["pos"], d["vel"], pref_vel=d["pref_vel"],
+                                    goals=d["goals"], nbr_out=nbr, lp_status=status)
+        g = dict(new_vel=nv[:, tidx].cpu().numpy().T.astype(np.float64),
+                 nbr=nbr[tidx].cpu().numpy(), status=status[tidx].cpu().numpy())
+        # then the step itself, in the benchmark's launch path
+        ctx.step(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], goals=d["goals"])
+        t += 1
+        o = oracle.velocities(pos0, vel0, pref0, w.offsets, w.params, goals=w.goals,
+                              agents=agents, neighbor_mode=1, **props(w))
+        # compare() indexes the GPU arrays by agent; hand it the sampled rows
+        gs = dict(new_vel=np.zeros((w.n, 2)), nbr=np.zeros((w.n, kmax), np.int64),
+                  status=np.zeros(w.n, np.uint8))
+        gs["new_vel"][idx] = g["new_vel"]
+        gs["nbr"][idx] = g["nbr"]
+        gs["status"][idx] = g["status"]
+        err = compare(w, gs, o, agents=agents, label="%s t=%d" % (label, tc))
+        flips = int((gs["status"][idx] != o["status"]).sum())
+        v1 = d["vel"][:, tidx].cpu().numpy().T.astype(np.float64)
+        p1 = d["pos"][:, tidx].cpu().numpy().T.astype(np.float64)
+        serr = np.abs(v1 - o["new_vel"]).max()
+        want_p = pos0.T[idx].astype(np.float64) + dt[scene[idx], None] * o["new_vel"]
+        perr = np.abs(p1 - want_p) - (dt[scene[idx], None] * TOL_V +
+                                      np.spacing(np.abs(want_p).astype(np.float32)))
+        assert serr < TOL_V, (label, tc, serr)
+        assert perr.max() <= 0, (label, tc)
+        rec.append((tc, float(max(err.max(), serr)), flips, int((o["status"] == 1).sum()),
+                    idx.size))
+    ctx.close()
+    say("%s summary (step, max |dv|, label flips, fallback, checked): %s" % (label, rec))
+    return rec
 
 
-def test_full_size_dense_sampled():
-    """1,048,576 agents at 2 /m^2, K = 16: sampled agents, launch path of the benchmark."""
-    say("case dense 1M")
-    w = scenes.dense_uniform()
-    step_parity(w, 3, sample=30000, label="dense1M")
+def test_deep_uniform_rsa():
+    """1,024 agents for 100 steps, every agent checked every 10th step."""
+    say("case deep uniform_rsa")
+    deep_parity(scenes.uniform_rsa(), list(range(0, 100, 10)) + [99], label="uniform_rsa")
 
 
-def test_full_size_batched_sampled():
-    """512 scenes (log-uniform sizes), sampled agents over all scenes."""
-    say("case batched 512 scenes")
-    w = scenes.batched()
-    step_parity(w, 2, sample=30000, label="batched")
+def test_deep_ring():
+    """The 65,536-agent ring for its whole 2,000 steps, every agent checked every
+    200th step and at the last: the ring compresses, so late states are the
+    overlapping, fallback-only regime of the lexicographic reading."""
+    say("case deep ring 65536")
+    deep_parity(scenes.ring(), list(range(0, 2000, 200)) + [1999], label="ring")
+
+
+def test_deep_dense_1m():
+    """1,048,576 agents at 2 /m^2 for 500 steps: 30,000 sampled agents every 50th
+    step and at the last, neighbour lists included (the evolved states the
+    benchmark times)."""
+    say("case deep dense 1M")
+    deep_parity(scenes.dense_uniform(), list(range(0, 500, 50)) + [499], sample=30000,
+                label="dense1M")
+
+
+def test_deep_batched():
+    """512 scenes for 300 steps: 30,000 sampled agents every 50th step and at the last."""
+    say("case deep batched 512 scenes")
+    deep_parity(scenes.batched(), list(range(0, 300, 50)) + [299], sample=30000,
+                label="batched")
+
+
+def test_full_size_ring_first_steps():
+    """The ring's first three steps, every agent, one step per call."""
+    say("case ring 65536 first steps")
+    step_parity(scenes.ring(), 3, label="ring", every=1)

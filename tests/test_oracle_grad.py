@@ -84,3 +84,55 @@ def test_single_agent_jvp_matches_central_differences(oracle_lib):
         checked += 1
         np.testing.assert_allclose(base[2:4], fd1, rtol=1e-4, atol=1e-6)
     assert checked > 200
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_f32_state_jvp(oracle_lib, seed):
+    """The float32-state branch of the trajectory derivative (the trajectory a
+    float32 state takes, the rounding differentiated as the identity).
+
+    - Its primal loss equals the loss of the float32 stepper that the step
+      parity uses (a separate driver: x <- f32(x + dt v'), v <- f32(v') with
+      fixed preferred velocities), to float64 rounding.
+    - On a short horizon, where the float32 and float64 trajectories stay
+      within rounding of each other and no discrete choice switches, its
+      derivative equals the float64-state derivative to 1e-5 of the size the
+      derivative can reach, 2 sqrt(L) |x'| with |x'| <= steps * dt * |delta|
+      (dL sums 2N terms of both signs, so the gap is set by their size, not by
+      their sum; the float32 state is rounded by about 1e-6 m a step and the
+      tangent moves with the state it is taken at), and central differences
+      of the float64 loss to 1e-3.
+    """
+    w = small_grad_scene(310 + seed)
+    rng = np.random.default_rng(40 + seed)
+    steps = 6
+    p = w.params[0]
+    vmax = np.array([np.float32(p.max_speed)], float)
+    tau = np.array([np.float32(p.time_horizon)], float)
+    pos0 = w.pos.astype(np.float64)
+    vel0 = w.vel.astype(np.float64)
+    pref = w.pref_vel.astype(np.float64)
+    x, v, _, _ = oracle_lib.step(w.pos, w.vel, w.pref_vel, w.offsets, w.params, n_steps=steps)
+    want = float(((x.astype(np.float64) - w.targets) ** 2).sum())
+    counted = 0
+    for d in range(8):
+        dp = rng.normal(size=pref.shape)
+        dv = rng.normal(size=1) * (d % 2)
+        dt_ = rng.normal(size=1) * ((d + 1) % 2)
+        L32, dL32 = oracle_lib.traj_jvp(pos0, vel0, pref, w.offsets, w.params, vmax, tau, steps,
+                                        w.targets, dp, dv, dt_, f32_state=True)
+        L64, dL64 = oracle_lib.traj_jvp(pos0, vel0, pref, w.offsets, w.params, vmax, tau, steps,
+                                        w.targets, dp, dv, dt_, f32_state=False)
+        assert abs(L32 - want) <= 1e-12 * abs(want), (L32, want)
+        assert abs(L32 - L64) <= 1e-5 * abs(L64)   # the two trajectories stay close
+        f = lambda eps: oracle_lib.traj_loss(pos0, vel0, pref + eps * dp, w.offsets, w.params,
+                                             vmax + eps * dv, tau + eps * dt_, steps, w.targets)
+        fd1 = (f(1e-6) - f(-1e-6)) / 2e-6
+        fd2 = (f(5e-7) - f(-5e-7)) / 1e-6
+        if abs(fd1 - fd2) > 1e-4 * max(1.0, abs(fd1)):
+            continue  # a discrete switch inside the interval
+        counted += 1
+        size = 2.0 * np.sqrt(L64) * steps * p.dt * np.sqrt((dp ** 2).sum() + dv @ dv + dt_ @ dt_)
+        assert abs(dL32 - dL64) <= 1e-5 * size, (d, dL32, dL64, size)
+        assert abs(dL32 - fd1) <= 1e-3 * max(1.0, abs(fd1)), (d, dL32, fd1)
+    assert counted >= 3

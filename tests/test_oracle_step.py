@@ -153,3 +153,50 @@ def test_scene_offsets_are_checked_against_the_agents(oracle_lib):
     with pytest.raises(ValueError):
         oracle_lib.step(w.pos, w.vel, w.pref_vel, [0, 49], w.params)
     oracle_lib.velocities(w.pos, w.vel, w.pref_vel, [0, 50], w.params)
+
+
+def test_lone_walkers_closed_form(oracle_lib):
+    """The Euler update and goal steering against their closed form: agents
+    far beyond each other's observation radius walk straight at their walking
+    speed s (or at v_max when v_max < s), covering min(s, v_max) * dt per step,
+    reach the goal on the step that leaves at most that far to go, and then
+    stand still.  Positions follow x_n = x_0 + n * v * dt up to one float32
+    rounding per step."""
+    dt = 0.1
+    cases = [  # start, goal, s, v_max
+        ((0.0, 0.0), (10.05, 0.0), 1.3, 1.5),
+        ((1000.0, 0.0), (1000.0, -7.03), 1.3, 1.0),       # clipped to v_max
+        ((-1000.0, 500.0), (-1000.0, 505.25), 2.0, 2.5),
+        ((500.0, -800.0), (496.13, -800.0), 0.7, 1.5),
+    ]  # distances off multiples of v * dt, so float32 drift cannot move the arrival step
+    n = len(cases)
+    pos = np.array([c[0] for c in cases], np.float32).T.copy()
+    goals = np.array([c[1] for c in cases], np.float32).T.copy()
+    # one scene per walker, so each has its own walking and max speed
+    params = [scenes.SceneParams(pref_speed=c[2], max_speed=c[3], dt=dt) for c in cases]
+    w = scenes.Workload("walkers", pos, np.zeros((2, n), np.float32), goals,
+                        np.zeros((2, n), np.float32), np.arange(n + 1), params, 1)
+    x, v, pref = w.pos, w.vel, w.pref_vel
+    dt32 = float(np.float32(dt))
+    speed = np.array([min(np.float32(c[2]), np.float32(c[3])) for c in cases], np.float64)
+    start = pos.astype(np.float64)
+    dist = np.linalg.norm(goals.astype(np.float64) - start, axis=0)
+    unit = (goals.astype(np.float64) - start) / dist
+    arrive = np.ceil(dist / (speed * dt32) - 1e-9).astype(int)
+    for step in range(1, int(arrive.max()) + 4):
+        x, v, pref, st = oracle_lib.step(x, v, pref, w.offsets, w.params, goals=w.goals)
+        assert np.all(st == 0)
+        for i in range(n):
+            walked = min(step * speed[i] * dt32, dist[i])
+            want = start[:, i] + walked * unit[:, i]
+            tol = (step + 1) * np.spacing(np.float32(np.abs(want).max() + 1.0))
+            assert np.abs(x[:, i] - want).max() <= tol, (i, step, x[:, i], want)
+            if step < arrive[i]:
+                # full speed along the goal direction
+                np.testing.assert_allclose(v[:, i], speed[i] * unit[:, i], atol=1e-6)
+            else:
+                # on the goal from the arrival step on, then standing (rounding only)
+                assert np.abs(x[:, i] - goals[:, i]).max() <= 2 * np.spacing(
+                    np.float32(np.abs(goals[:, i]).max())), (i, step)
+                if step > arrive[i]:
+                    assert np.abs(v[:, i]).max() <= 1e-3
