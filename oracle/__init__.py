@@ -294,6 +294,9 @@ def _grad_lib():
         L.oracle_step_jvp.restype = None
         L.oracle_choice_jvp.argtypes = [ctypes.c_int] + [P] * 6 + [F64] * 13 + [P]
         L.oracle_choice_jvp.restype = ctypes.c_int
+        L.oracle_traj_curve.argtypes = [I64, P, P, P, I32, P, P, P, P, I32, P, P, P, P, P, P, P,
+                                        P]
+        L.oracle_traj_curve.restype = None
         L._grad_ready = True
     return L
 
@@ -350,3 +353,25 @@ def step_jvp(pos, vel, pref, offsets, params, dpos, dvel, dpref, dvmax, dtau, ra
                                 params_array(params), _ptr(dpos), _ptr(dvel), _ptr(dpref),
                                 _ptr(dvmax), _ptr(dtau), ag, _ptr(op), _ptr(ov))
     return op, ov
+
+
+def traj_curve(pos0, vel0, pref, offsets, params, vmax, tau, n_steps, targets, dpref=None,
+               dvmax=None, dtau=None, radius=None, max_speed=None):
+    """A float64 trajectory step by step: (loss after each step [n_steps],
+    directional derivative of that loss along (dpref, dvmax, dtau) [n_steps]
+    (zeros without a tangent), hash of each step's discrete decisions
+    [n_steps] uint64).  With a tangent the run is a complex step; the
+    decisions are the primal's either way."""
+    pos0, vel0, pref, targets, vmax, tau, dpref, dvmax, dtau = map(
+        _f64, (pos0, vel0, pref, targets, vmax, tau, dpref, dvmax, dtau))
+    ag, keep = _agents(radius, max_speed, None)
+    n = pos0.shape[1]
+    loss = np.zeros(n_steps)
+    dloss = np.zeros(n_steps)
+    tape = np.zeros(n_steps, np.uint64)
+    _grad_lib().oracle_traj_curve(n, _ptr(pos0), _ptr(vel0), _ptr(pref), len(params),
+                                  _ptr(_offsets(offsets, n, len(params))), params_array(params),
+                                  _ptr(vmax), _ptr(tau), int(n_steps), _ptr(targets),
+                                  _ptr(dpref), _ptr(dvmax), _ptr(dtau), ag, _ptr(loss),
+                                  _ptr(dloss), _ptr(tape))
+    return loss, dloss, tape

@@ -297,13 +297,13 @@ int oracle_halfplane(double Px, double Py, double Vx, double Vy, double R, doubl
 int oracle_project(int m, const halfplane *h, double shift, double vmax, double vhx, double vhy,
                    double *ox, double *oy)
 {
-    return project(m, h, shift, vmax, vhx, vhy, ox, oy);
+    return project(m, h, shift, vmax, vhx, vhy, ox, oy, NULL);
 }
 
 /* The least penetration by enumeration; see min_max(). */
 double oracle_min_max(int m, const halfplane *h, double vmax, double *ox, double *oy)
 {
-    return min_max(m, h, vmax, ox, oy);
+    return min_max(m, h, vmax, ox, oy, NULL);
 }
 
 /* ------------------------------------------------------------------ */
@@ -351,7 +351,7 @@ int oracle_agent_velocity(int64_t n_total, const float *pos, const float *vel,
     }
     return choose(m, Px, Py, Vx, Vy, Rs, first, (double)vx[i], (double)vy[i], p->time_horizon,
                   p->dt, ag_vmax(ag, p, i), vhx, vhy, ox, oy, dstar, hp_out ? hp_out : hbuf,
-                  branch_out);
+                  branch_out, NULL);
 }
 
 /*
@@ -379,7 +379,7 @@ int oracle_choice_jvp(int m, const double *P, const double *dP, const double *V,
     double complex ox, oy, d;
     int st = choose_cx(m, Px, Py, Vx, Vy, Rc, first, vix + I * h * dvix, viy + I * h * dviy,
                        tau + I * h * dtau, dt, vmax + I * h * dvmax, vhx + I * h * dvhx,
-                       vhy + I * h * dvhy, &ox, &oy, &d, hb, NULL);
+                       vhy + I * h * dvhy, &ox, &oy, &d, hb, NULL, NULL);
     out[0] = creal(ox);
     out[1] = creal(oy);
     out[2] = cimag(ox) / h;
@@ -569,7 +569,7 @@ void oracle_life_step(int64_t n_total, float *pos, float *vel, float *pref, cons
 #define DEFINE_TRAJ_STEP(R_T, SUF, RE_, FIRST_CHOOSE)                                           \
     static void traj_step##SUF(int64_t n, R_T *pos, R_T *vel, const R_T *pref, int32_t n_scenes,  \
                                const int64_t *off, const oracle_params *par, const R_T *vmax_s,   \
-                               const R_T *tau_s, const oracle_agents *ag)                         \
+                               const R_T *tau_s, const oracle_agents *ag, uint64_t *ahash)        \
     {                                                                                             \
         float *p32 = (float *)malloc(sizeof(float) * 2 * (size_t)(n ? n : 1));                   \
         R_T *nv = (R_T *)malloc(sizeof(R_T) * 2 * (size_t)(n ? n : 1));                           \
@@ -597,7 +597,11 @@ void oracle_life_step(int64_t n_total, float *pos, float *vel, float *pref, cons
             }                                                                                     \
             /* a per-agent max speed is a constant; the scene's is the leaf */                    \
             const R_T vmax_i = ag && ag->max_speed ? (R_T)ag->max_speed[i] : vmax_s[s];           \
+            int32_t branch[64];                                                                   \
+            int codes[3];                                                                         \
+            int status;                                                                           \
             FIRST_CHOOSE;                                                                         \
+            if (ahash) ahash[i] = decisions_hash(m, ids, branch, status, codes);                  \
         }                                                                                         \
         for (int64_t i = 0; i < n; ++i) {                                                         \
             double dt = par[scene_of(n_scenes, off, i)].dt;                                       \
@@ -612,16 +616,42 @@ void oracle_life_step(int64_t n_total, float *pos, float *vel, float *pref, cons
         free(p32);                                                                                \
     }
 
+/*
+ * Every discrete decision of one agent's step, folded into 64 bits: the
+ * neighbour list, each half-plane's branch, feasibility and the candidate
+ * that won each program.  Two steps whose hashes agree took the same branch
+ * of the piecewise-smooth step map (up to a hash collision).
+ */
+static uint64_t tape_mix(uint64_t h, uint64_t x)
+{
+    uint64_t z = h ^ (x * 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+static uint64_t decisions_hash(int32_t m, const int64_t *ids, const int32_t *branch, int status,
+                               const int *codes)
+{
+    uint64_t h = tape_mix(0x243f6a8885a308d3ull, (uint64_t)m);
+    for (int32_t t = 0; t < m; ++t)
+        h = tape_mix(h, ((uint64_t)ids[t] << 8) | (uint64_t)(branch[t] & 0xff));
+    h = tape_mix(h, (uint64_t)status);
+    for (int c = 0; c < 3; ++c) h = tape_mix(h, (uint64_t)(int64_t)codes[c]);
+    return h;
+}
+
 DEFINE_TRAJ_STEP(double, _d, (double), {
     halfplane hb[64];
-    choose(m, Px, Py, Vx, Vy, Rs, first, vel[i], vel[n + i], tau_s[s], p->dt, vmax_i, pref[i],
-           pref[n + i], &nv[2 * i], &nv[2 * i + 1], NULL, hb, NULL);
+    status = choose(m, Px, Py, Vx, Vy, Rs, first, vel[i], vel[n + i], tau_s[s], p->dt, vmax_i,
+                    pref[i], pref[n + i], &nv[2 * i], &nv[2 * i + 1], NULL, hb, branch, codes);
 })
 
 DEFINE_TRAJ_STEP(double complex, _c, creal, {
     halfplane_t_cx hb[64];
-    choose_cx(m, Px, Py, Vx, Vy, Rs, first, vel[i], vel[n + i], tau_s[s], p->dt, vmax_i,
-              pref[i], pref[n + i], &nv[2 * i], &nv[2 * i + 1], NULL, hb, NULL);
+    status = choose_cx(m, Px, Py, Vx, Vy, Rs, first, vel[i], vel[n + i], tau_s[s], p->dt,
+                       vmax_i, pref[i], pref[n + i], &nv[2 * i], &nv[2 * i + 1], NULL, hb, branch,
+                       codes);
 })
 
 /*
@@ -639,7 +669,7 @@ double oracle_traj_loss(int64_t n, const double *pos0, const double *vel0, const
     memcpy(pos, pos0, sizeof(double) * 2 * (size_t)n);
     memcpy(vel, vel0, sizeof(double) * 2 * (size_t)n);
     for (int32_t t = 0; t < n_steps; ++t)
-        traj_step_d(n, pos, vel, pref, n_scenes, off, par, vmax_s, tau_s, ag);
+        traj_step_d(n, pos, vel, pref, n_scenes, off, par, vmax_s, tau_s, ag, NULL);
     double L = 0.0;
     for (int64_t i = 0; i < 2 * n; ++i) L += (pos[i] - targets[i]) * (pos[i] - targets[i]);
     free(pos);
@@ -676,7 +706,7 @@ void oracle_traj_jvp(int64_t n, const double *pos0, const double *vel0, const do
         ta[s] = tau_s[s] + I * h * (dtau ? dtau[s] : 0.0);
     }
     for (int32_t t = 0; t < n_steps; ++t) {
-        traj_step_c(n, pos, vel, pr, n_scenes, off, par, vm, ta, ag);
+        traj_step_c(n, pos, vel, pr, n_scenes, off, par, vm, ta, ag, NULL);
         if (f32_state) /* keep the primal on float32 states (as the GPU stores them) */
             for (int64_t i = 0; i < 2 * n; ++i) {
                 pos[i] = (double)(float)creal(pos[i]) + I * cimag(pos[i]);
@@ -720,7 +750,7 @@ void oracle_step_jvp(int64_t n, const float *pos, const float *vel, const float 
         vm[s] = (double)par[s].max_speed + I * h * dvmax[s];
         ta[s] = (double)par[s].time_horizon + I * h * dtau[s];
     }
-    traj_step_c(n, p, v, pr, n_scenes, off, par, vm, ta, ag);
+    traj_step_c(n, p, v, pr, n_scenes, off, par, vm, ta, ag, NULL);
     for (int64_t i = 0; i < 2 * n; ++i) {
         dpos_out[i] = cimag(p[i]) / h;
         dvel_out[i] = cimag(v[i]) / h;
@@ -730,4 +760,85 @@ void oracle_step_jvp(int64_t n, const float *pos, const float *vel, const float 
     free(pr);
     free(vm);
     free(ta);
+}
+
+/*
+ * A float64 trajectory from (pos0, vel0) with fixed preferred velocities,
+ * step by step: loss_t[t] = sum_i |x_i - y_i|^2 after t + 1 steps and
+ * tape_t[t] = the hash of every decision step t took (in agent order).  With
+ * a tangent (dpref, dvmax, dtau, any of them non-NULL) the trajectory runs by
+ * complex step and dloss_t[t] is the loss's directional derivative after
+ * t + 1 steps along that tangent; the decisions are the primal's.  Used to
+ * count central differences only where no decision switches.
+ */
+void oracle_traj_curve(int64_t n, const double *pos0, const double *vel0, const double *pref,
+                       int32_t n_scenes, const int64_t *off, const oracle_params *par,
+                       const double *vmax_s, const double *tau_s, int32_t n_steps,
+                       const double *targets, const double *dpref, const double *dvmax,
+                       const double *dtau, const oracle_agents *ag, double *loss_t,
+                       double *dloss_t, uint64_t *tape_t)
+{
+    uint64_t *ah = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+    const int tangent = dpref || dvmax || dtau;
+    if (!tangent) {
+        double *pos = (double *)malloc(sizeof(double) * 2 * (size_t)(n ? n : 1));
+        double *vel = (double *)malloc(sizeof(double) * 2 * (size_t)(n ? n : 1));
+        memcpy(pos, pos0, sizeof(double) * 2 * (size_t)n);
+        memcpy(vel, vel0, sizeof(double) * 2 * (size_t)n);
+        for (int32_t t = 0; t < n_steps; ++t) {
+            traj_step_d(n, pos, vel, pref, n_scenes, off, par, vmax_s, tau_s, ag, ah);
+            /* summed in long double: central differences divide the loss's
+             * rounding by 2h, so it must stay far below L */
+            long double L = 0.0L;
+            for (int64_t i = 0; i < 2 * n; ++i) {
+                const double e = pos[i] - targets[i];
+                L += (long double)e * (long double)e;
+            }
+            uint64_t hs = tape_mix(0, (uint64_t)t);
+            for (int64_t i = 0; i < n; ++i) hs = tape_mix(hs, ah[i]);
+            if (loss_t) loss_t[t] = (double)L;
+            if (dloss_t) dloss_t[t] = 0.0;
+            if (tape_t) tape_t[t] = hs;
+        }
+        free(pos);
+        free(vel);
+        free(ah);
+        return;
+    }
+    const double h = 1e-30;
+    double complex *pos = (double complex *)malloc(sizeof(double complex) * 2 * (size_t)(n ? n : 1));
+    double complex *vel = (double complex *)malloc(sizeof(double complex) * 2 * (size_t)(n ? n : 1));
+    double complex *pr = (double complex *)malloc(sizeof(double complex) * 2 * (size_t)(n ? n : 1));
+    double complex *vm = (double complex *)malloc(sizeof(double complex) * (size_t)n_scenes);
+    double complex *ta = (double complex *)malloc(sizeof(double complex) * (size_t)n_scenes);
+    for (int64_t i = 0; i < 2 * n; ++i) {
+        pos[i] = pos0[i];
+        vel[i] = vel0[i];
+        pr[i] = pref[i] + I * h * (dpref ? dpref[i] : 0.0);
+    }
+    for (int s = 0; s < n_scenes; ++s) {
+        vm[s] = vmax_s[s] + I * h * (dvmax ? dvmax[s] : 0.0);
+        ta[s] = tau_s[s] + I * h * (dtau ? dtau[s] : 0.0);
+    }
+    for (int32_t t = 0; t < n_steps; ++t) {
+        traj_step_c(n, pos, vel, pr, n_scenes, off, par, vm, ta, ag, ah);
+        /* L and its tangent 2 e . e' summed in long double, as above */
+        long double Lr = 0.0L, Li = 0.0L;
+        for (int64_t i = 0; i < 2 * n; ++i) {
+            const double er = creal(pos[i]) - targets[i], ei = cimag(pos[i]) / h;
+            Lr += (long double)er * (long double)er;
+            Li += 2.0L * (long double)er * (long double)ei;
+        }
+        uint64_t hs = tape_mix(0, (uint64_t)t);
+        for (int64_t i = 0; i < n; ++i) hs = tape_mix(hs, ah[i]);
+        if (loss_t) loss_t[t] = (double)Lr;
+        if (dloss_t) dloss_t[t] = (double)Li;
+        if (tape_t) tape_t[t] = hs;
+    }
+    free(pos);
+    free(vel);
+    free(pr);
+    free(vm);
+    free(ta);
+    free(ah);
 }

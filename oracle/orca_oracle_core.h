@@ -105,15 +105,16 @@ typedef struct {
     int found;
     REAL bx, by;
     double bd;
+    int code; /* which candidate won (a discrete choice; see project()) */
 } FN(best_t);
 
 static void FN(consider)(FN(best_t) *b, int m, const FN(halfplane_t) *h, REAL shift, REAL vmax,
-                         REAL px, REAL py, REAL vhx, REAL vhy)
+                         REAL px, REAL py, REAL vhx, REAL vhy, int code)
 {
     if (!isfinite(RE(px)) || !isfinite(RE(py))) return;
     if (!FN(feasible)(m, h, shift, vmax, px, py)) return;
     double d = RE((px - vhx) * (px - vhx) + (py - vhy) * (py - vhy));
-    if (!b->found || d < b->bd) { b->found = 1; b->bx = px; b->by = py; b->bd = d; }
+    if (!b->found || d < b->bd) { b->found = 1; b->bx = px; b->by = py; b->bd = d; b->code = code; }
 }
 
 /*
@@ -123,28 +124,35 @@ static void FN(consider)(FN(best_t) *b, int m, const FN(halfplane_t) *h, REAL sh
  * is vhat itself, the radial clip of vhat, the projection of vhat onto one
  * boundary line, a line-circle crossing, or a line-line crossing; all of them
  * are tried.  Returns 1 and writes the minimiser if the set is non-empty,
- * else 0.
+ * else 0.  *which (nullable) names the candidate that won: 0 vhat, 1 its
+ * clip, 2 + 4k the foot on line k, 3 + 4k and 4 + 4k its circle crossings,
+ * 100000 + 64k + l the crossing of lines k < l; -1 when empty.
  */
 static int FN(project)(int m, const FN(halfplane_t) *h, REAL shift, REAL vmax, REAL vhx, REAL vhy,
-                       REAL *ox, REAL *oy)
+                       REAL *ox, REAL *oy, int *which)
 {
     FN(best_t) b;
     b.found = 0;
     b.bd = 0.0;
-    FN(consider)(&b, m, h, shift, vmax, vhx, vhy, vhx, vhy);
+    b.code = -1;
+    FN(consider)(&b, m, h, shift, vmax, vhx, vhy, vhx, vhy, 0);
     REAL vl = SQRT(vhx * vhx + vhy * vhy);
-    if (RE(vl) > 0.0) FN(consider)(&b, m, h, shift, vmax, vmax * vhx / vl, vmax * vhy / vl, vhx, vhy);
+    if (RE(vl) > 0.0)
+        FN(consider)(&b, m, h, shift, vmax, vmax * vhx / vl, vmax * vhy / vl, vhx, vhy, 1);
     for (int k = 0; k < m; ++k) {
         /* boundary line: n_k.v = c_k */
         REAL c = h[k].nx * h[k].qx + h[k].ny * h[k].qy - shift;
         REAL t = c - (h[k].nx * vhx + h[k].ny * vhy);
-        FN(consider)(&b, m, h, shift, vmax, vhx + t * h[k].nx, vhy + t * h[k].ny, vhx, vhy);
+        FN(consider)(&b, m, h, shift, vmax, vhx + t * h[k].nx, vhy + t * h[k].ny, vhx, vhy,
+                     2 + 4 * k);
         REAL hh = vmax * vmax - c * c;
         if (RE(hh) >= 0.0) {
             REAL r = SQRT(hh);
             REAL dx = -h[k].ny, dy = h[k].nx;
-            FN(consider)(&b, m, h, shift, vmax, c * h[k].nx + r * dx, c * h[k].ny + r * dy, vhx, vhy);
-            FN(consider)(&b, m, h, shift, vmax, c * h[k].nx - r * dx, c * h[k].ny - r * dy, vhx, vhy);
+            FN(consider)(&b, m, h, shift, vmax, c * h[k].nx + r * dx, c * h[k].ny + r * dy, vhx,
+                         vhy, 3 + 4 * k);
+            FN(consider)(&b, m, h, shift, vmax, c * h[k].nx - r * dx, c * h[k].ny - r * dy, vhx,
+                         vhy, 4 + 4 * k);
         }
     }
     for (int k = 0; k < m; ++k) {
@@ -155,9 +163,10 @@ static int FN(project)(int m, const FN(halfplane_t) *h, REAL shift, REAL vmax, R
             if (RE(det) == 0.0) continue;
             REAL px = (ck * h[l].ny - cl * h[k].ny) / det;
             REAL py = (h[k].nx * cl - h[l].nx * ck) / det;
-            FN(consider)(&b, m, h, shift, vmax, px, py, vhx, vhy);
+            FN(consider)(&b, m, h, shift, vmax, px, py, vhx, vhy, 100000 + 64 * k + l);
         }
     }
+    if (which) *which = b.code;
     if (!b.found) return 0;
     *ox = b.bx;
     *oy = b.by;
@@ -176,12 +185,12 @@ static REAL FN(max_violation)(int m, const FN(halfplane_t) *h, REAL vx, REAL vy)
 }
 
 static void FN(consider_mm)(int m, const FN(halfplane_t) *h, REAL vmax, REAL vx, REAL vy,
-                            int *found, REAL *bf, REAL *bx, REAL *by)
+                            int *found, REAL *bf, REAL *bx, REAL *by, int code, int *bcode)
 {
     if (!isfinite(RE(vx)) || !isfinite(RE(vy))) return;
     if (RE(vx * vx + vy * vy) > RE(vmax * vmax) * (1.0 + 1e-12) + 1e-12) return;
     REAL f = FN(max_violation)(m, h, vx, vy);
-    if (!*found || RE(f) < RE(*bf)) { *found = 1; *bf = f; *bx = vx; *by = vy; }
+    if (!*found || RE(f) < RE(*bf)) { *found = 1; *bf = f; *bx = vx; *by = vy; *bcode = code; }
 }
 
 /*
@@ -189,14 +198,19 @@ static void FN(consider_mm)(int m, const FN(halfplane_t) *h, REAL vmax, REAL vx,
  * that least penetrates the half-planes).  The minimum of this convex
  * piecewise-linear function over the disc sits where three pieces are equal,
  * where two pieces are equal on the circle, or on the circle at the point
- * that maximises a single n_k.v (v = vmax n_k); all are tried.
+ * that maximises a single n_k.v (v = vmax n_k); all are tried.  *which
+ * (nullable) names the candidate that won: k for vmax n_k, 1000 + 2(64k + l)
+ * (+1) for the two circle points of rows k < l, 1000000 + 64(64k + l) + p for
+ * the triple k < l < p; -1 when m = 0.
  */
-static REAL FN(min_max)(int m, const FN(halfplane_t) *h, REAL vmax, REAL *ox, REAL *oy)
+static REAL FN(min_max)(int m, const FN(halfplane_t) *h, REAL vmax, REAL *ox, REAL *oy,
+                        int *which)
 {
-    int found = 0;
+    int found = 0, code = -1;
     REAL bf = 0.0, bx = 0.0, by = 0.0;
     for (int k = 0; k < m; ++k)
-        FN(consider_mm)(m, h, vmax, vmax * h[k].nx, vmax * h[k].ny, &found, &bf, &bx, &by);
+        FN(consider_mm)(m, h, vmax, vmax * h[k].nx, vmax * h[k].ny, &found, &bf, &bx, &by, k,
+                        &code);
     for (int k = 0; k < m; ++k) {
         REAL ck = h[k].nx * h[k].qx + h[k].ny * h[k].qy;
         for (int l = k + 1; l < m; ++l) {
@@ -209,8 +223,10 @@ static REAL FN(min_max)(int m, const FN(halfplane_t) *h, REAL vmax, REAL *ox, RE
             REAL hh = vmax * vmax - (px * px + py * py);
             if (RE(hh) < 0.0) continue;
             REAL r = SQRT(hh / a2);
-            FN(consider_mm)(m, h, vmax, px - r * ay, py + r * ax, &found, &bf, &bx, &by);
-            FN(consider_mm)(m, h, vmax, px + r * ay, py - r * ax, &found, &bf, &bx, &by);
+            FN(consider_mm)(m, h, vmax, px - r * ay, py + r * ax, &found, &bf, &bx, &by,
+                            1000 + 2 * (64 * k + l), &code);
+            FN(consider_mm)(m, h, vmax, px + r * ay, py - r * ax, &found, &bf, &bx, &by,
+                            1001 + 2 * (64 * k + l), &code);
             for (int p = l + 1; p < m; ++p) {
                 REAL cp = h[p].nx * h[p].qx + h[p].ny * h[p].qy;
                 /* n.v + t = c for the three pieces (Cramer's rule) */
@@ -221,10 +237,12 @@ static REAL FN(min_max)(int m, const FN(halfplane_t) *h, REAL vmax, REAL *ox, RE
                 if (RE(det) == 0.0) continue;
                 REAL dxn = ck * (a22 - a32) - a12 * (cl - cp) + (cl * a32 - a22 * cp);
                 REAL dyn = a11 * (cl - cp) - ck * (a21 - a31) + (a21 * cp - cl * a31);
-                FN(consider_mm)(m, h, vmax, dxn / det, dyn / det, &found, &bf, &bx, &by);
+                FN(consider_mm)(m, h, vmax, dxn / det, dyn / det, &found, &bf, &bx, &by,
+                                1000000 + 64 * (64 * k + l) + p, &code);
             }
         }
     }
+    if (which) *which = code;
     *ox = bx;
     *oy = by;
     return found ? bf : (REAL)(-INFINITY);
@@ -240,8 +258,11 @@ static REAL FN(min_max)(int m, const FN(halfplane_t) *h, REAL vmax, REAL *ox, RE
 static int FN(choose)(int m, const REAL *Px, const REAL *Py, const REAL *Vx, const REAL *Vy,
                       const REAL *Rs, const int *first, REAL vix, REAL viy, REAL tau, REAL dt,
                       REAL vmax, REAL vhx, REAL vhy, REAL *ox, REAL *oy, REAL *dstar,
-                      FN(halfplane_t) *h, int32_t *branch)
+                      FN(halfplane_t) *h, int32_t *branch, int *codes)
 {
+    /* codes (nullable, 3): the winning candidate of the projection, of the
+     * least penetration and of the relaxed projection (-1: not run) */
+    int c0 = -1, c1 = -1, c2 = -1;
     for (int t = 0; t < m; ++t) {
         REAL ux, uy, nx, ny;
         int code = FN(obstacle)(Px[t], Py[t], Vx[t], Vy[t], Rs[t], tau, dt, first[t], &ux, &uy,
@@ -252,16 +273,18 @@ static int FN(choose)(int m, const REAL *Px, const REAL *Py, const REAL *Vx, con
         h[t].nx = nx;
         h[t].ny = ny;
     }
-    if (FN(project)(m, h, 0.0, vmax, vhx, vhy, ox, oy)) {
+    if (FN(project)(m, h, 0.0, vmax, vhx, vhy, ox, oy, &c0)) {
         if (dstar) *dstar = NAN;
+        if (codes) { codes[0] = c0; codes[1] = c1; codes[2] = c2; }
         return 0;
     }
     REAL mx, my;
-    REAL d = FN(min_max)(m, h, vmax, &mx, &my);
+    REAL d = FN(min_max)(m, h, vmax, &mx, &my, &c1);
     if (dstar) *dstar = d;
-    if (!FN(project)(m, h, d + ORC_DELTA, vmax, vhx, vhy, ox, oy)) {
+    if (!FN(project)(m, h, d + ORC_DELTA, vmax, vhx, vhy, ox, oy, &c2)) {
         *ox = mx;
         *oy = my;
     }
+    if (codes) { codes[0] = c0; codes[1] = c1; codes[2] = c2; }
     return 1;
 }

@@ -163,3 +163,68 @@ def test_trajectory_gradient_with_and_without_the_kept_recording():
     for a, b in zip(*grads):
         assert np.allclose(a, b, rtol=1e-5, atol=1e-6 * np.abs(a).max())
     assert np.abs(grads[0][0]).max() > 0
+
+
+@pytest.mark.parametrize("horizon", [2, 8])
+def test_adjoint_against_central_differences(horizon):
+    """The GPU adjoint of the 4,096-agent trajectory against float64 central
+    differences of the reference's loss (h = 1e-4 and h / 2, Richardson
+    combined), along 16 random unit directions in (preferred velocities, v_max,
+    tau) and along v_max and tau, counting only directions whose every
+    decision at theta +- h delta matches theta's over the horizon.  Two steps:
+    all 18 count; eight steps: the longest horizon at which half still do."""
+    torch = _torch()
+    from paper_1908_10107_amd import autograd, orca
+    say("case adjoint vs central differences, 4096 agents x %d steps" % horizon)
+    w = scenes.grad()
+    d = orca.to_device(w)
+    p = w.params[0]
+    pref = d["pref_vel"].clone().requires_grad_(True)
+    vmax = torch.tensor([p.max_speed], device="cuda", requires_grad=True)
+    tau = torch.tensor([p.time_horizon], device="cuda", requires_grad=True)
+    spec = autograd.TrajectorySpec(offsets=list(w.offsets), params=list(w.params),
+                                   n_steps=horizon, segment=horizon)
+    pos, vel = autograd.trajectory(d["pos"], d["vel"], pref, vmax, tau, spec)
+    y = torch.from_numpy(w.targets).cuda()
+    ((pos.double() - y.double()) ** 2).sum().backward()
+    torch.cuda.synchronize()
+    g_pref = pref.grad.cpu().numpy().astype(np.float64)
+    g_vmax = float(vmax.grad.cpu()[0])
+    g_tau = float(tau.grad.cpu()[0])
+    spec.ctx.close()
+    h = 1e-4
+    pos0, vel0 = w.pos.astype(np.float64), w.vel.astype(np.float64)
+    pr = w.pref_vel.astype(np.float64)
+    vm = np.array([np.float32(p.max_speed)], float)
+    ta = np.array([np.float32(p.time_horizon)], float)
+    curve = lambda a, b, c: oracle.traj_curve(pos0, vel0, a, w.offsets, w.params, b, c, horizon,
+                                              w.targets)
+    _, _, tape0 = curve(pr, vm, ta)
+    rng = np.random.default_rng(scenes.BASE_SEED + 4)
+    dirs = []
+    for k in range(16):
+        v = rng.normal(size=pr.size + 2)
+        v /= np.linalg.norm(v)
+        dirs.append(("rand%d" % k, v[:-2].reshape(pr.shape), v[-2], v[-1]))
+    dirs += [("vmax", np.zeros_like(pr), 1.0, 0.0), ("tau", np.zeros_like(pr), 0.0, 1.0)]
+    counted = 0
+    worst = 0.0
+    for name, dp, dv, dt_ in dirs:
+        runs = []
+        for e in (h, -h, h / 2, -h / 2):
+            L, _, tp = curve(pr + e * dp, vm + e * dv, ta + e * dt_)
+            runs.append((L[-1], np.array_equal(tp, tape0)))
+        if not all(r[1] for r in runs):
+            continue  # a decision switches inside the interval
+        counted += 1
+        fd = (runs[0][0] - runs[1][0]) / (2 * h)
+        fd2 = (runs[2][0] - runs[3][0]) / h
+        rich = (4 * fd2 - fd) / 3
+        mine = float((g_pref * dp).sum() + g_vmax * dv + g_tau * dt_)
+        err = abs(mine - rich) / abs(rich)
+        worst = max(worst, err)
+        say("  %-6s adjoint %.9g  central differences %.9g  rel %.2e" % (name, mine, rich, err))
+        assert err <= 1e-3, (name, mine, rich)
+    say("  %d of %d directions counted, worst relative difference %.2e"
+        % (counted, len(dirs), worst))
+    assert counted >= (18 if horizon == 2 else 9)
