@@ -14,6 +14,7 @@ stream) and the CPU reference's rate on a bounded sample of the same state.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -32,16 +33,17 @@ FP64_PEAK_TFLOPS = 78.6
 # Algorithmic work of each stage.
 #   binning (HBM): bbox 8 + key pass 28 + scatter 56 = 92 B per agent, + 12 B per cell.
 #   neighbours (HBM figure): own row 24 + list 4K + count 4 = 28 + 4K B per agent.
-#   half-planes + 2D LP (FP64 ALU): 29.2 K + 15.2 K operations per agent
+#   half-planes + 2D LP (FP64 ALU): 29.2 K + 15.5 K operations per agent
 #     (half-plane construction; projection and the choice of the fallback's
-#     first plane; 710 at K = 16).
-#   fallback (FP64 ALU): 28.2 K operations per fallback agent (451 at K = 16).
-# The FP64 operation counts were taken from the programs as written (an add,
-# subtract, multiply, divide or square root is one; a fused multiply-add two)
-# on a dense evolved state; see the roofline section of the design notes.
+#     first plane; 715 at K = 16).
+#   fallback (FP64 ALU): 28.7 K operations per fallback agent (460 at K = 16).
+# The FP64 operation counts come from the kernels' own programs built for the
+# host with their work-counting hooks (csrc/orca_work_count.cpp), run on 4,000
+# agents of an evolved dense state; tests/test_work_counts.py recounts them
+# and holds these constants to 3%.
 HP_OPS_PER_K = 29.2
-LP2_OPS_PER_K = 15.2
-FB_OPS_PER_K = 28.2
+LP2_OPS_PER_K = 15.5
+FB_OPS_PER_K = 28.7
 
 
 def stage_roofline(stage: int, ms: float, n: int, k: int, cells: int, n_fallback: float):
@@ -83,6 +85,44 @@ def profiled_traffic(kernel: str):
     return None
 
 
+def profiled_lane_use():
+    """VALU lane utilisation per kernel from the committed counter summary,
+    or None when the kernel sources have changed since it was taken."""
+    import hashlib
+    try:
+        text = open(PROFILE_MD).read()
+    except OSError:
+        return None
+    d = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            d.update(fh.read())
+    if "kernel-source-sha256: %s " % d.hexdigest()[:16] not in text:
+        return None
+    out = {}
+    for line in text.splitlines():
+        if line.startswith("lane-use "):
+            k, v = line[len("lane-use "):].split(": ")
+            out[k] = float(v)
+    return out or None
+
+
+def grid_cells(w, cells_per_nd=2, margin=1.0 + 1.0 / 1024.0):
+    """Grid cells of the current positions: per scene, cells of side
+    neighbor_dist * margin / cells_per_nd over the bounding box."""
+    c = 0
+    for s, p in enumerate(w.params):
+        lo, hi = int(w.offsets[s]), int(w.offsets[s + 1])
+        if hi <= lo:
+            c += 1
+            continue
+        x = w.pos[:, lo:hi].astype(np.float64)
+        side = float(np.float32(p.neighbor_dist)) * margin / cells_per_nd
+        ext = x.max(axis=1) - x.min(axis=1)
+        c += int((np.floor(ext[0] / side) + 1) * (np.floor(ext[1] / side) + 1))
+    return c
+
+
 def make_workload(name: str):
     from paper_1908_10107_amd import scenes
     if name == "dense_uniform":
@@ -96,10 +136,35 @@ def make_workload(name: str):
     raise SystemExit("unknown workload %s" % name)
 
 
+def host_cpu():
+    """Logical CPUs of the host, those this process may use, and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(nproc=os.cpu_count(), usable=usable, model=model)
+
+
 def cpu_baseline(w, min_seconds: float):
-    """The reference's rate on whole steps of the same workload from its
-    initial state, stepped one at a time until ``min_seconds`` have passed."""
+    """The reference (float64 C, OpenMP over agents) on the host's cores.
+
+    value: whole steps of the timed workload from its initial state (binning,
+    velocities, Euler, steering), stepped one at a time until ``min_seconds``
+    have passed, on every thread.  Also: one thread on a 100,000-agent sample
+    of the same state; the 1,024-agent square's whole 100-step run; the
+    4,096-agent 200-step trajectory with its forward-mode derivative."""
     import oracle
+    from paper_1908_10107_amd import scenes
+    threads = oracle.threads()
     pos, vel, pref = w.pos, w.vel, w.pref_vel
     steps = 0
     t0 = time.perf_counter()
@@ -109,10 +174,83 @@ def cpu_baseline(w, min_seconds: float):
         dt = time.perf_counter() - t0
         if dt >= min_seconds or steps >= 200:
             break
-    return dict(value=w.n * steps / dt, unit="agent-steps/s", cores=oracle.threads(),
-                kind="oracle",
-                sample="%d whole steps of all %d agents from the initial state, %.1f s"
-                       % (steps, w.n, dt))
+    out = dict(value=w.n * steps / dt, unit="agent-steps/s", cores=threads, kind="oracle",
+               sample="%d whole steps of all %d agents from the initial state, %.1f s"
+                      % (steps, w.n, dt), host=host_cpu())
+    # one thread, velocities of a sample of the same initial state
+    rng = np.random.default_rng(1)
+    m = min(w.n, 100000)
+    agents = np.sort(rng.choice(w.n, m, replace=False))
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params, goals=w.goals,
+                          agents=agents)
+        d1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    out["one_thread"] = dict(value=m / d1, unit="agent-steps/s", cores=1,
+                             sample="velocities of %d sampled agents of the initial state "
+                                    "(binning included), %.1f s" % (m, d1))
+    # the 1,024-agent square, all 100 steps
+    u = scenes.uniform_rsa()
+    t0 = time.perf_counter()
+    oracle.step(u.pos, u.vel, u.pref_vel, u.offsets, u.params, goals=u.goals, n_steps=u.steps)
+    du = time.perf_counter() - t0
+    out["uniform_rsa_1024x100"] = dict(value=u.n * u.steps / du, unit="agent-steps/s",
+                                       cores=threads, seconds=round(du, 3))
+    # the differentiable workload: forward with one forward-mode tangent
+    g = scenes.grad()
+    p = g.params[0]
+    r = np.random.default_rng(2)
+    t0 = time.perf_counter()
+    oracle.traj_jvp(g.pos.astype(np.float64), g.vel.astype(np.float64),
+                    g.pref_vel.astype(np.float64), g.offsets, g.params,
+                    np.array([p.max_speed], float), np.array([p.time_horizon], float), g.steps,
+                    g.targets, r.normal(size=g.pref_vel.shape), np.ones(1), np.ones(1))
+    dg = time.perf_counter() - t0
+    out["grad_4096x200_forward_mode"] = dict(value=g.n * g.steps / dg, unit="agent-steps/s",
+                                             cores=threads, seconds=round(dg, 3))
+    return out
+
+
+def full_length_forms(launch):
+    """Each workload over its whole length from t = 0 in one call (one
+    orca_step of all steps, or graph replays for the 512 scenes)."""
+    import torch
+    from paper_1908_10107_amd import orca, scenes
+    out = {}
+    for name, make, graph in (("uniform_rsa_1024x100", scenes.uniform_rsa, False),
+                              ("ring_65536x2000", scenes.ring, False),
+                              ("dense_1M_x500", scenes.dense_uniform, False),
+                              ("batched_512x300", scenes.batched, True)):
+        w = make()
+        kmax = max(p.max_neighbors for p in w.params)
+        d = orca.to_device(w)
+        ctx = orca.Context(max_agents=w.n, max_scenes=w.n_scenes, k_max=kmax)
+        if launch:
+            ctx.set_launch(*launch)
+        fn = ctx.step_graph if graph else ctx.step
+        kw = {} if graph else {"save_tape": False}
+        if graph:
+            # capture the graph (one step), then put the initial state back in
+            # place: the timed replays start at t = 0 on the captured pointers
+            init = {k: d[k].clone() for k in ("pos", "vel", "pref_vel")}
+            ctx.step_graph(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"],
+                           goals=d["goals"], n_steps=1)
+            for k in init:
+                d[k].copy_(init[k])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], goals=d["goals"],
+           n_steps=w.steps, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.close()
+        out[name] = {"value": w.n * w.steps / dt, "ms_per_step": 1e3 * dt / w.steps,
+                     "agents": w.n, "scenes": w.n_scenes, "steps": "0-%d" % (w.steps - 1),
+                     "launch": "graph replays" if graph else "one orca_step call"}
+    return out
 
 
 def batched_forms(steps: int, no_autotune: bool):
@@ -127,7 +265,7 @@ def batched_forms(steps: int, no_autotune: bool):
     tuned = None
     if not no_autotune:
         ctx.build_grid(w.offsets, w.params, d["pos"])
-        tuned = ctx.autotune(d["pos"], d["vel"], d["pref_vel"], goals=d["goals"], reps=2)
+        tuned = ctx.autotune(d["pos"], d["vel"], d["pref_vel"], goals=d["goals"], reps=5)
     ctx.step_graph(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], goals=d["goals"],
                    n_steps=3)
     torch.cuda.synchronize()
@@ -279,11 +417,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="the CPU reference steps the workload until this much time has passed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="plain,batched,adjoint,hetero,spawn",
+    ap.add_argument("--forms", default="plain,batched,adjoint,hetero,spawn,full",
                     help="comma list: plain (always), batched (512 scenes, graph replay vs "
                          "per-scene plain steps), adjoint (forward + adjoint), hetero "
                          "(people of different sizes and speeds), spawn (spawning and "
-                         "removal)")
+                         "removal), full (each workload over its whole length from t = 0)")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None,
@@ -315,7 +453,7 @@ def main():
         ctx.set_launch(*tuned)
     elif not args.no_autotune:
         ctx.build_grid(w.offsets, w.params, st["pos"])
-        tuned = ctx.autotune(st["pos"], st["vel"], st["pref"], goals=base["goals"], reps=2)
+        tuned = ctx.autotune(st["pos"], st["vel"], st["pref"], goals=base["goals"], reps=5)
     if args.warmup:
         step(args.warmup)
     torch.cuda.synchronize()
@@ -341,7 +479,9 @@ def main():
     avg = [m / max(passes, 1) for m in ms]
     fb_avg = fb / max(passes, 1)
     dom = int(np.argmax(avg))
-    cells = 4 * w.n  # upper bound of the cell budget; the 12 B/cell term is small
+    # cells of the grid at the end of the timed steps (the 12 B/cell term is small)
+    state_now = dataclasses.replace(w, pos=st["pos"].cpu().numpy())
+    cells = grid_cells(state_now)
     stages = {orca.STAGE_NAMES[i]: round(avg[i], 4) for i in range(orca.PROF_STAGES)}
     bound, achieved, peak, unit = stage_roofline(dom, avg[dom], w.n, kmax, cells, fb_avg)
     others = {}
@@ -353,9 +493,17 @@ def main():
     kname = ("k_key", "k_knn<%d>" % kdisp, "k_lp<%d,0>" % kdisp,
              "k_fallback<%d,0>" % kdisp)[dom]
     traffic = profiled_traffic(kname) if args.workload == "dense_uniform" else None
+    # the whole step against HBM: 144 B per agent + 12 B per cell, each array
+    # touched once (state, sort, neighbour state, outputs, goals)
+    step_bytes = 144.0 * w.n + 12.0 * cells
+    step_gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
     roofline = dict(bound=bound, achieved=round(achieved, 4), peak=peak, unit=unit,
                     frac=round(achieved / peak, 6), traffic=traffic, traffic_unit="B/launch",
                     kernel=kname,
+                    step_hbm={"bytes_per_step": step_bytes, "cells": cells,
+                              "achieved": round(step_gbs, 2), "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 6)},
+                    lane_use=profiled_lane_use(),
                     stage_ms=stages, stages=others,
                     fallback_agents_per_step=round(fb_avg, 1))
 
@@ -380,6 +528,8 @@ def main():
         forms.update(hetero_forms(50, tuned if args.launch else None))
     if "spawn" in args.forms.split(","):
         forms.update(spawn_forms(100, tuned if args.launch else None))
+    if "full" in args.forms.split(","):
+        forms.update(full_length_forms(tuned))
 
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -399,6 +549,8 @@ def main():
         "config": {"workload": args.workload, "agents": w.n, "scenes": w.n_scenes,
                    "max_neighbors": kmax,
                    "neighbor_dist": w.params[0].neighbor_dist,
+                   "cell": "neighbor_dist * (1 + 2^-10) / 2 (two cells per neighbor_dist; "
+                           "same neighbours as cells of neighbor_dist)",
                    "state": "f32", "lp": "f64", "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -64,6 +64,8 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
         L.oracle_dist2_f32.argtypes = [F32, F32, F32, F32]
         L.oracle_dist2_f32.restype = F32
         L.oracle_knn_brute.argtypes = [I64, P, I64, I64, I64, F32, I32, P, P]
@@ -127,6 +129,11 @@ def params_array(params):
 
 def threads() -> int:
     return lib().oracle_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of later calls (n <= 0: one per processor)."""
+    lib().oracle_set_threads(int(n))
 
 
 def dist2_f32(xi, yi, xj, yj) -> float:

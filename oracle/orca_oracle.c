@@ -102,6 +102,16 @@ int oracle_threads(void)
 #endif
 }
 
+/* Use n threads in later calls from this thread (n <= 0: one per processor). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Neighbour selection                                                 */
 /* ------------------------------------------------------------------ */

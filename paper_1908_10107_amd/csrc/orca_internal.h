@@ -44,57 +44,8 @@ struct Counters {
     uint32_t removed;
 };
 
-// An agent whose projection was empty, with what the fallback needs to
-// finish it without touching the agent arrays again: sorted index, id, number
-// of half-planes, the row at which the projection failed, the line and bound
-// that fix the optimum of the rows before it (an Active, as int8), the most
-// violated row from the failed one on, that optimum, the preferred velocity,
-// max speed, dt and position.  Rows are numbered as in the neighbour list;
-// the stash holds them in the order of stash_position().
-struct FallbackItem {
-    int32_t s, id;
-    int8_t m, fail, line, src;
-    int8_t worst, pad8[3];
-    double vx, vy, vhx, vhy;
-    float vmax, dt, mex, mey;
-};
-static_assert(sizeof(FallbackItem) == 64, "one fallback record per 64-byte line");
-
-// Order in which the fallback takes an agent's rows (the stash order): the
-// rows that fix the projection's last optimum (line, then src) first, the
-// other rows before the failed one next, then the most violated row from the
-// failed one on, then the rest.  The programs' results do not depend on the
-// order, only their cost does: started this way, the least-penetration
-// program meets few violations after its first plane.
-__host__ __device__ __forceinline__ int stash_position(int k, const FallbackItem &it)
-{
-    // selects only: the kernels evaluate it for every row of a wave at once
-    const int fail = it.fail, line = it.line, src = it.src, worst = it.worst;
-    const int nf = (line >= 0 ? 1 : 0) + (src >= 0 ? 1 : 0);
-    int before = nf + k - ((src >= 0 && src < k) ? 1 : 0) - ((line >= 0 && line < k) ? 1 : 0);
-    before = k == src ? (line >= 0 ? 1 : 0) : before;
-    before = k == line ? 0 : before;
-    const int after = k == worst ? fail : k + (k < worst ? 1 : 0);
-    return k < fail ? before : after;
-}
-
-// Inverse of stash_position (negative codes pass through: they name no row).
-__host__ __device__ __forceinline__ int stash_row(int p, const FallbackItem &it)
-{
-    const int fail = it.fail, line = it.line, src = it.src, worst = it.worst;
-    if (p < 0) return p;
-    if (p < fail) {
-        const int nf = (line >= 0 ? 1 : 0) + (src >= 0 ? 1 : 0);
-        if (p < nf) return p == 0 ? (line >= 0 ? line : src) : src;
-        int k = p - nf;
-        if (src >= 0 && src <= k) ++k;  // src < line when both are rows
-        if (line >= 0 && line <= k) ++k;
-        return k;
-    }
-    if (p == fail) return worst;
-    const int k = p - 1;
-    return k >= worst ? k + 1 : k;
-}
+// FallbackItem (the record of an agent whose projection was empty) and the
+// stash order of its rows (stash_position / stash_row) are in orca_lp.h.
 
 // Optional per-agent properties, indexed by agent (nullptr: the scene's
 // value).  srad holds the radii in cell order when radius is given.

@@ -815,20 +815,7 @@ __attribute__((amdgpu_waves_per_eu(KMAX <= kLpRegRows ? 3 : 1))) void k_lp(
             it.line = (int8_t)act.line;
             it.src = (int8_t)act.src;
             // the most violated row from the failed one on, at the last optimum
-            int worst = fail;
-            double wv = -1.0e300;
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                if (k >= fail && k < m) {
-                    const double2 nk = rows.N(k);
-                    const double viol = rows.B(k) - (nk.x * vx + nk.y * vy);
-                    if (viol > wv) {
-                        wv = viol;
-                        worst = k;
-                    }
-                }
-            }
-            it.worst = (int8_t)worst;
+            it.worst = (int8_t)worst_row<KMAX>(rows, fail, m, vx, vy);
             it.vx = vx;
             it.vy = vy;
             it.vhx = vhx;
@@ -977,43 +964,12 @@ __device__ __forceinline__ void fallback_items(RS &rows, const OutArgs &out, int
             if (k < m) rows.set(k, gn[k], gb[k]);
             else rows.set(k, make_double2(0.0, 0.0), 0.0);
         }
-        const double vmax = (double)it.vmax;
         double vx = it.vx, vy = it.vy;
         int plane = -1;
-        Active dact;
-        const double d = lp3_least_penetration<KMAX>(rows, m, fail, vmax, vx, vy, &plane, &dact);
-        FrontRows F;
-        F.pos[0] = plane;
-        F.pos[1] = dact.line;
-        F.pos[2] = dact.src;
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            F.n[u] = make_double2(0.0, 0.0);
-            F.b[u] = 0.0;
-            if (F.pos[u] < 0) F.pos[u] = -1;
-        }
-        // copy the rows that fix d*: one pass with the same row index on every
-        // lane (a per-lane index would move register-held rows to memory)
-#pragma unroll 1
-        for (int k = 0; k < KMAX; ++k) {
-            const double2 nk = rows.N(k);
-            const double bk = rows.B(k);
-#pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                if (F.pos[u] == k) {
-                    F.n[u] = nk;
-                    F.b[u] = bk;
-                }
-            }
-        }
-        double wx, wy;
-        Active ract;
-        const bool ok = lp2_project_front<KMAX>(rows, m, F, d + kRelax, vmax, it.vhx, it.vhy, wx,
-                                                wy, &ract) < 0;
-        if (ok) {
-            vx = wx;
-            vy = wy;
-        }
+        Active dact, ract;
+        bool ok;
+        const double d = fallback_velocity<KMAX>(rows, m, fail, (double)it.vmax, it.vhx, it.vhy,
+                                                 vx, vy, &plane, &dact, &ract, &ok);
         if (MODE == kModeRec) {
             TapeCode tc{};
             tc.status = 1;

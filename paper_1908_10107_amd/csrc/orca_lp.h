@@ -27,9 +27,14 @@ inline double2 make_double2(double x, double y) { return double2{x, y}; }
 // Always inlined: a row store held in registers must not escape into a call.
 #define ORCA_HDI ORCA_HD __attribute__((always_inline))
 
-// Work-counting hook for offline analysis builds; compiles to nothing here.
+// Work-counting hooks for the host build that counts the programs' work per
+// agent (ORCA_COUNT: one event; ORCA_COUNT_N: n events); they compile to
+// nothing in the library.
 #ifndef ORCA_COUNT
 #define ORCA_COUNT(what)
+#endif
+#ifndef ORCA_COUNT_N
+#define ORCA_COUNT_N(what, n)
 #endif
 
 namespace orca {
@@ -78,6 +83,13 @@ ORCA_HD inline void obstacle_exit(double Px, double Py, double Vx, double Vy, do
     const double w2 = wx * wx + wy * wy;
     const double wP = wx * Px + wy * Py;
     const bool circle = !apart || (wP < 0.0 && wP * wP > R2 * w2);
+    if (!apart) {
+        ORCA_COUNT(hp_overlap);
+    } else if (circle) {
+        ORCA_COUNT(hp_arc);
+    } else {
+        ORCA_COUNT(hp_leg);
+    }
     // Each case takes one square root and two quotients by one divisor: |w|
     // and w / |w| on the circle; the leg length L and the leg direction
     // (L P -+ R P_perp) / |P|^2 on a leg (left, sg = +1, if w is left of P).
@@ -141,6 +153,58 @@ constexpr double kRelax = 1e-5;  // relaxation of the least-penetration second s
 struct Active {
     int line, src;
 };
+
+// An agent whose projection was empty, with what the fallback needs to
+// finish it without touching the agent arrays again: sorted index, id, number
+// of half-planes, the row at which the projection failed, the line and bound
+// that fix the optimum of the rows before it (an Active, as int8), the most
+// violated row from the failed one on, that optimum, the preferred velocity,
+// max speed, dt and position.  Rows are numbered as in the neighbour list;
+// the stash holds them in the order of stash_position().
+struct FallbackItem {
+    int32_t s, id;
+    int8_t m, fail, line, src;
+    int8_t worst, pad8[3];
+    double vx, vy, vhx, vhy;
+    float vmax, dt, mex, mey;
+};
+static_assert(sizeof(FallbackItem) == 64, "one fallback record per 64-byte line");
+
+// Order in which the fallback takes an agent's rows (the stash order): the
+// rows that fix the projection's last optimum (line, then src) first, the
+// other rows before the failed one next, then the most violated row from the
+// failed one on, then the rest.  The programs' results do not depend on the
+// order, only their cost does: started this way, the least-penetration
+// program meets few violations after its first plane.
+ORCA_HDI inline int stash_position(int k, const FallbackItem &it)
+{
+    // selects only: the kernels evaluate it for every row of a wave at once
+    const int fail = it.fail, line = it.line, src = it.src, worst = it.worst;
+    const int nf = (line >= 0 ? 1 : 0) + (src >= 0 ? 1 : 0);
+    int before = nf + k - ((src >= 0 && src < k) ? 1 : 0) - ((line >= 0 && line < k) ? 1 : 0);
+    before = k == src ? (line >= 0 ? 1 : 0) : before;
+    before = k == line ? 0 : before;
+    const int after = k == worst ? fail : k + (k < worst ? 1 : 0);
+    return k < fail ? before : after;
+}
+
+// Inverse of stash_position (negative codes pass through: they name no row).
+ORCA_HDI inline int stash_row(int p, const FallbackItem &it)
+{
+    const int fail = it.fail, line = it.line, src = it.src, worst = it.worst;
+    if (p < 0) return p;
+    if (p < fail) {
+        const int nf = (line >= 0 ? 1 : 0) + (src >= 0 ? 1 : 0);
+        if (p < nf) return p == 0 ? (line >= 0 ? line : src) : src;
+        int k = p - nf;
+        if (src >= 0 && src <= k) ++k;  // src < line when both are rows
+        if (line >= 0 && line <= k) ++k;
+        return k;
+    }
+    if (p == fail) return worst;
+    const int k = p - 1;
+    return k >= worst ? k + 1 : k;
+}
 
 // Feasible interval lo <= s <= hi of a 1D program, each end kept as a
 // fraction and compared by cross-multiplication, so adding a constraint costs
@@ -444,6 +508,8 @@ ORCA_HDI inline double lp3_least_penetration(const RS &L, int m, int start, doub
             const bool hit = ((left >> u) & 1u) != 0u && !(nu.x * vx + nu.y * vy + t >= L.B(u));
             k = hit ? u : k;
         }
+        // a lane on its own tests its untested rows up to the violated one
+        ORCA_COUNT_N(lp3_check, __builtin_popcount(left & (k < KB ? rows_below(k + 1) : ~0u)));
         if (k >= KB) break;
         left &= ~rows_below(k + 1);
         ORCA_COUNT(lp3_plane);
@@ -552,11 +618,82 @@ ORCA_HDI inline int lp2_project_front(const RS &L, int m, const FrontRows &F, do
             const bool hit = ((left >> u) & 1u) != 0u && !(nu.x * vx + nu.y * vy >= L.B(u) - relax);
             k = hit ? u : k;
         }
+        ORCA_COUNT_N(lp2_check, __builtin_popcount(left & (k < KB ? rows_below(k + 1) : ~0u)));
         if (k >= KB) break;
         left &= ~rows_below(k + 1);
         line_step(L.NL(k), L.BL(k) - relax, k, 3, k);
     }
     return fail;
+}
+
+// The row most violated at (vx, vy) among rows fail..m-1 of a store (the
+// fallback's first plane is taken there); fail if none is.
+template <int KB, class RS>
+ORCA_HDI inline int worst_row(const RS &rows, int fail, int m, double vx, double vy)
+{
+    int worst = fail;
+    double wv = -1.0e300;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        if (k >= fail && k < m) {
+            ORCA_COUNT(fail_row_check);
+            const double2 nk = rows.N(k);
+            const double viol = rows.B(k) - (nk.x * vx + nk.y * vy);
+            if (viol > wv) {
+                wv = viol;
+                worst = k;
+            }
+        }
+    }
+    return worst;
+}
+
+// The fallback's choice for one agent (section 3, infeasible case), its rows
+// in stash order in store RS and (vx, vy) the projection's last optimum,
+// where rows 0..fail-1 hold: d* by the least-penetration program, then the
+// point closest to vhat within d* + kRelax of every half-plane, with the rows
+// that fix d* taken first (the relaxed optimum lies where they cross, so the
+// other rows are rarely violated).  Sets (vx, vy) to the result and returns
+// d*; *relaxed_ok is false when the relaxed projection was empty (the
+// least-penetration point stands).  plane, dact, ract: what fixed the two
+// programs' optima, rows named by stash position.
+template <int KB, class RS>
+ORCA_HDI inline double fallback_velocity(const RS &rows, int m, int fail, double vmax, double vhx,
+                                         double vhy, double &vx, double &vy, int *plane,
+                                         Active *dact, Active *ract, bool *relaxed_ok)
+{
+    const double d = lp3_least_penetration<KB>(rows, m, fail, vmax, vx, vy, plane, dact);
+    FrontRows F;
+    F.pos[0] = *plane;
+    F.pos[1] = dact->line;
+    F.pos[2] = dact->src;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        F.n[u] = make_double2(0.0, 0.0);
+        F.b[u] = 0.0;
+        if (F.pos[u] < 0) F.pos[u] = -1;
+    }
+    // copy the rows that fix d*: one pass with the same row index on every
+    // lane (a per-lane index would move register-held rows to memory)
+#pragma unroll 1
+    for (int k = 0; k < KB; ++k) {
+        const double2 nk = rows.N(k);
+        const double bk = rows.B(k);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            if (F.pos[u] == k) {
+                F.n[u] = nk;
+                F.b[u] = bk;
+            }
+        }
+    }
+    double wx, wy;
+    *relaxed_ok = lp2_project_front<KB>(rows, m, F, d + kRelax, vmax, vhx, vhy, wx, wy, ract) < 0;
+    if (*relaxed_ok) {
+        vx = wx;
+        vy = wy;
+    }
+    return d;
 }
 
 }  // namespace orca
