@@ -123,6 +123,16 @@ def grid_cells(w, cells_per_nd=2, margin=1.0 + 1.0 / 1024.0):
     return c
 
 
+def apply_launch(ctx, launch):
+    """Fixed launch shapes: (knn_block, fallback waves per CU[, agents per lane,
+    velocity waves per CU[, fallback work units]]) as orca_autotune returns them."""
+    if not launch:
+        return
+    ctx.set_launch(launch[0], launch[1])
+    if len(launch) >= 4:
+        ctx.set_kernels(launch[2], launch[3], launch[4] if len(launch) >= 5 else 0)
+
+
 def make_workload(name: str):
     from paper_1908_10107_amd import scenes
     if name == "dense_uniform":
@@ -228,8 +238,7 @@ def full_length_forms(launch):
         kmax = max(p.max_neighbors for p in w.params)
         d = orca.to_device(w)
         ctx = orca.Context(max_agents=w.n, max_scenes=w.n_scenes, k_max=kmax)
-        if launch:
-            ctx.set_launch(*launch)
+        apply_launch(ctx, launch)
         fn = ctx.step_graph if graph else ctx.step
         kw = {} if graph else {"save_tape": False}
         if graph:
@@ -355,8 +364,7 @@ def hetero_forms(steps: int, launch):
     d = orca.to_device(w)
     ctx = orca.Context(max_agents=w.n, max_scenes=1, k_max=w.params[0].max_neighbors)
     ctx.set_agents(d["radius"], d["max_speed"], d["pref_speed"])
-    if launch:
-        ctx.set_launch(*launch)
+    apply_launch(ctx, launch)
     step = lambda k: ctx.step(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"],
                               goals=d["goals"], n_steps=k)
     step(5)
@@ -388,8 +396,7 @@ def spawn_forms(steps: int, launch):
     d = orca.to_device(w)
     state = torch.zeros(w.n, dtype=torch.uint8, device="cuda")
     ctx = orca.Context(max_agents=w.n, max_scenes=1, k_max=w.params[0].max_neighbors)
-    if launch:
-        ctx.set_launch(*launch)
+    apply_launch(ctx, launch)
     ctx.set_lifecycle(d["spawn_step"], state, 0)
     step = lambda k: ctx.step_graph(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"],
                                     goals=d["goals"], n_steps=k)
@@ -425,7 +432,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", default=None,
-                    help="KNN_BLOCK,FALLBACK_WAVES_PER_CU: fixed launch shapes instead of autotuning")
+                    help="KNN_BLOCK,FALLBACK_WAVES_PER_CU[,AGENTS_PER_LANE,VELOCITY_WAVES_PER_CU"
+                         "[,FALLBACK_WORK_UNITS]]: fixed launch shapes instead of autotuning "
+                         "(agents per lane 0: split neighbour and LP kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise copy of 256 MiB (reads and writes known bytes) "
                          "to scale hardware byte counters")
@@ -450,7 +459,7 @@ def main():
     tuned = None
     if args.launch:
         tuned = tuple(int(x) for x in args.launch.split(","))
-        ctx.set_launch(*tuned)
+        apply_launch(ctx, tuned)
     elif not args.no_autotune:
         ctx.build_grid(w.offsets, w.params, st["pos"])
         tuned = ctx.autotune(st["pos"], st["vel"], st["pref"], goals=base["goals"], reps=5)
@@ -554,8 +563,10 @@ def main():
                    "state": "f32", "lp": "f64", "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "autotune": None if tuned is None else {"knn_block": tuned[0],
-                                                "fallback_waves_per_cu": tuned[1]},
+        "autotune": None if tuned is None else dict(zip(
+            ("knn_block", "fallback_waves_per_cu", "agents_per_lane", "velocity_waves_per_cu",
+             "fallback_work_units"),
+            tuned)),
         "forms": forms,
     }
     print(json.dumps(line), flush=True)

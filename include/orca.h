@@ -169,14 +169,23 @@ int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
                     const float *goals, int32_t n_steps);
 
 /*
- * Pick the launch shapes for the current workload: threads per neighbour
- * block (64, 128, 256, 512) and persistent fallback waves per compute unit
- * (4, 8, 16, 32, i.e. how many fallback agents each lane takes on), by timing
- * velocity passes with HIP events: per candidate one untimed pass, then the
- * fastest of reps passes for each stage.  Needs orca_build_grid
- * on pos first; writes only new_vel (device [2, N], scratch).  The choice is
- * kept in the context and returned in choice[2] (nullable).  Waits for the
- * stream.
+ * Pick the launch shapes for the current workload by timing velocity passes
+ * with HIP events (per candidate one untimed pass, then the fastest of reps
+ * passes for each stage):
+ *   - threads per neighbour block (64, 128, 256, 512) and persistent
+ *     fallback waves per compute unit (4, 8, 16, 32, i.e. how many fallback
+ *     agents each lane takes on);
+ *   - the velocity kernels (see orca_set_kernels): the split neighbour and
+ *     LP kernels, or the fused persistent kernel with 1, 2 or 4 agents per
+ *     lane and 8 or 12 waves per compute unit, whichever runs the neighbour
+ *     and LP stages fastest;
+ *   - the fallback with or without work units (with: 6 waves per compute
+ *     unit; neighbour caps up to 16).
+ * Needs orca_build_grid on pos first; writes only new_vel (device [2, N],
+ * scratch).  The choice is kept in the context and returned in choice[5]
+ * (nullable): knn_block, fallback waves per CU, agents per lane (0 = split
+ * kernels), velocity waves per CU, fallback work units (0 or 1).  Waits for
+ * the stream.
  */
 int orca_autotune(orca_ctx *ctx, const float *pos, const float *vel, const float *pref_vel,
                   const float *goals, float *new_vel, int32_t reps, int32_t *choice);
@@ -235,6 +244,27 @@ int orca_population(orca_ctx *ctx, int32_t *step, int64_t *present, int64_t *rem
  * Results do not depend on them.  Errors: EINVAL.
  */
 int orca_set_launch(orca_ctx *ctx, int32_t knn_block, int32_t fb_waves_per_cu);
+
+/*
+ * Select kernel variants (results do not depend on them).
+ * agents_per_lane: 0 runs the neighbour search and the half-planes + 2D LP
+ *   (section 3) as two kernels with the neighbour lists stored in between
+ *   (the default); 1, 2 or 4 runs both in one persistent kernel with each
+ *   agent's neighbour list in registers: its one-wave blocks
+ *   (velocity_waves_per_cu per compute unit, 1..32) take tiles of
+ *   64 * agents_per_lane agents in cell order from one atomic queue per XCD
+ *   (the XCD's contiguous share of the tiles, then the others' once its own
+ *   is empty).  Plain passes only: recorded steps and steps with spawning
+ *   and removal use the two kernels.
+ * fallback_work_units: 1 runs the least-penetration fallback with work units
+ *   (section 3: the recompute of a new velocity cut into equal pieces that
+ *   idle threads take over; here the 1D programs on violated lines of the
+ *   plane subproblems, split across groups of 4 lanes); 0 (the default) has
+ *   each lane run its own.  Used for neighbour caps up to 16.
+ * Errors: EINVAL.
+ */
+int orca_set_kernels(orca_ctx *ctx, int32_t agents_per_lane, int32_t velocity_waves_per_cu,
+                     int32_t fallback_work_units);
 
 /*
  * Vector-Jacobian product of recorded step tape_step (0-based, of the last

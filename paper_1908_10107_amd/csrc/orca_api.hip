@@ -98,6 +98,8 @@ struct orca_ctx {
 
     // launch shapes (orca_autotune picks them)
     int32_t knn_block = 256, fb_waves_per_cu = 16;
+    int32_t vel_apl = 0, vel_waves_per_cu = 12;  // velocity kernels (orca_set_kernels)
+    int32_t fb_work_units = 0;                   // fallback with work units (orca_set_kernels)
 
     // step graph: one captured step replayed by orca_step_graph
     hipStream_t cap_stream = nullptr;
@@ -105,7 +107,7 @@ struct orca_ctx {
     hipGraphExec_t graph_exec = nullptr;
     const void *graph_key[9] = {};
     uint64_t graph_scene_version = 0, scene_version = 0;
-    int32_t graph_knn_block = 0, graph_fb = 0;
+    int32_t graph_knn_block = 0, graph_fb = 0, graph_apl = -1, graph_vw = 0, graph_wu = -1;
 
     char err[512] = {0};
 };
@@ -235,6 +237,9 @@ orca::Plan make_plan(const orca_ctx *ctx)
     p.cus = ctx->cus;
     p.knn_block = ctx->knn_block;
     p.fb_waves_per_cu = ctx->fb_waves_per_cu;
+    p.vel_apl = ctx->vel_apl;
+    p.vel_waves_per_cu = ctx->vel_waves_per_cu;
+    p.fb_work_units = ctx->fb_work_units;
     p.max_cells = ctx->max_cells;
     p.off = ctx->off;
     p.sp = ctx->sp;
@@ -612,7 +617,9 @@ int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
     const bool fresh = ctx->graph_exec && memcmp(key, ctx->graph_key, sizeof(key)) == 0 &&
                        ctx->graph_scene_version == ctx->scene_version &&
                        ctx->graph_knn_block == ctx->knn_block &&
-                       ctx->graph_fb == ctx->fb_waves_per_cu;
+                       ctx->graph_fb == ctx->fb_waves_per_cu && ctx->graph_apl == ctx->vel_apl &&
+                       ctx->graph_vw == ctx->vel_waves_per_cu &&
+                       ctx->graph_wu == ctx->fb_work_units;
     if (!fresh) {
         drop_graph(ctx);
         if (!ctx->cap_stream) HIP_OK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
@@ -645,6 +652,9 @@ int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
         ctx->graph_scene_version = ctx->scene_version;
         ctx->graph_knn_block = ctx->knn_block;
         ctx->graph_fb = ctx->fb_waves_per_cu;
+        ctx->graph_apl = ctx->vel_apl;
+        ctx->graph_vw = ctx->vel_waves_per_cu;
+        ctx->graph_wu = ctx->fb_work_units;
     }
     for (int32_t t = 0; t < n_steps; ++t) HIP_OK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
     return ORCA_OK;
@@ -659,42 +669,86 @@ int orca_autotune(orca_ctx *ctx, const float *pos, const float *vel, const float
         return fail(ctx, ORCA_ESTATE, "orca_build_grid must be called first on the same pos");
     static const int32_t blocks[] = {64, 128, 256, 512};
     static const int32_t waves[] = {4, 8, 16, 32};
+    static const int32_t apls[] = {1, 2, 4};
+    static const int32_t vwaves[] = {8, 12};
     const bool was = ctx->profiling;
     int rc = orca_profile(ctx, 1);
     if (rc != ORCA_OK) return rc;
-    double best_knn = 1e300, best_fb = 1e300;
-    int32_t knn_block = ctx->knn_block, fb = ctx->fb_waves_per_cu;
-    for (int t = 0; t < 4; ++t) {
-        ctx->knn_block = blocks[t];
-        ctx->fb_waves_per_cu = waves[t];
-        // one untimed pass with the new shapes, then the fastest of reps timed
-        // passes per stage (a sum would carry the noise of every pass)
-        double knn_ms = 1e300, fb_ms = 1e300;
+    const int32_t apl0 = ctx->vel_apl, vw0 = ctx->vel_waves_per_cu, wu0 = ctx->fb_work_units;
+    const int32_t fb0 = ctx->fb_waves_per_cu;
+    ctx->fb_work_units = 0;
+    // one untimed pass with the candidate's shapes, then the fastest of reps
+    // timed passes per stage (a sum would carry the noise of every pass)
+    auto time_stages = [&](double (&best)[ORCA_PROF_STAGES]) {
+        for (double &b : best) b = 1e300;
         for (int32_t r = 0; r <= reps && rc == ORCA_OK; ++r) {
             orca_profile(ctx, 1);
             rc = orca_compute_velocities(ctx, pos, vel, pref_vel, goals, new_vel, nullptr, nullptr);
-            if (r > 0) {
-                knn_ms = std::min(knn_ms, ctx->stage_ms[1]);
-                fb_ms = std::min(fb_ms, ctx->stage_ms[3]);
-            }
+            if (r > 0)
+                for (int i = 0; i < ORCA_PROF_STAGES; ++i) best[i] = std::min(best[i], ctx->stage_ms[i]);
         }
+    };
+    // split kernels: neighbour block size and fallback waves (independent stages)
+    double best_knn = 1e300, best_lp = 1e300, best_fb = 1e300;
+    int32_t knn_block = ctx->knn_block, fb = ctx->fb_waves_per_cu;
+    ctx->vel_apl = 0;
+    for (int t = 0; t < 4 && rc == ORCA_OK; ++t) {
+        ctx->knn_block = blocks[t];
+        ctx->fb_waves_per_cu = waves[t];
+        double st[ORCA_PROF_STAGES];
+        time_stages(st);
         if (rc != ORCA_OK) break;
-        if (knn_ms < best_knn) {
-            best_knn = knn_ms;
+        if (st[1] < best_knn) {
+            best_knn = st[1];
             knn_block = blocks[t];
         }
-        if (fb_ms < best_fb) {
-            best_fb = fb_ms;
+        best_lp = std::min(best_lp, st[2]);
+        if (st[3] < best_fb) {
+            best_fb = st[3];
             fb = waves[t];
         }
     }
     ctx->knn_block = knn_block;
     ctx->fb_waves_per_cu = fb;
+    // the fused velocity kernel: agents per lane and waves per CU, against
+    // the split kernels' neighbour + LP stages
+    double best_vel = best_knn + best_lp;
+    int32_t apl = 0, vw = vw0;
+    for (int a = 0; a < 3 && rc == ORCA_OK; ++a)
+        for (int w = 0; w < 2 && rc == ORCA_OK; ++w) {
+            ctx->vel_apl = apls[a];
+            ctx->vel_waves_per_cu = vwaves[w];
+            double st[ORCA_PROF_STAGES];
+            time_stages(st);
+            if (rc == ORCA_OK && st[1] + st[2] < best_vel) {
+                best_vel = st[1] + st[2];
+                apl = apls[a];
+                vw = vwaves[w];
+            }
+        }
+    ctx->vel_apl = rc == ORCA_OK ? apl : apl0;
+    ctx->vel_waves_per_cu = rc == ORCA_OK ? vw : vw0;
+    // the fallback with work units (its LDS holds it to 6 waves per CU)
+    int32_t wu = 0;
+    if (rc == ORCA_OK && ctx->kmax_cur <= 16) {
+        const int32_t fb_plain = ctx->fb_waves_per_cu;
+        ctx->fb_work_units = 1;
+        ctx->fb_waves_per_cu = 6;
+        double st[ORCA_PROF_STAGES];
+        time_stages(st);
+        if (rc == ORCA_OK && st[3] < best_fb) wu = 1;
+        else ctx->fb_waves_per_cu = fb_plain;
+    }
+    ctx->fb_work_units = rc == ORCA_OK ? wu : wu0;
+    if (rc != ORCA_OK) ctx->fb_waves_per_cu = fb0;
     orca_profile(ctx, was ? 1 : 0);
     if (rc != ORCA_OK) return rc;
     if (choice) {
-        choice[0] = knn_block;
-        choice[1] = fb;
+        choice[0] = ctx->knn_block;
+        choice[1] = ctx->fb_waves_per_cu;
+        choice[2] = ctx->vel_apl;
+        choice[3] = ctx->vel_waves_per_cu;
+        choice[4] = ctx->fb_work_units;
     }
     return ORCA_OK;
 }
@@ -708,6 +762,23 @@ int orca_set_launch(orca_ctx *ctx, int32_t knn_block, int32_t fb_waves_per_cu)
         return fail(ctx, ORCA_EINVAL, "fb_waves_per_cu must be in 1..64");
     ctx->knn_block = knn_block;
     ctx->fb_waves_per_cu = fb_waves_per_cu;
+    return ORCA_OK;
+}
+
+int orca_set_kernels(orca_ctx *ctx, int32_t agents_per_lane, int32_t velocity_waves_per_cu,
+                     int32_t fallback_work_units)
+{
+    if (!ctx) return ORCA_EINVAL;
+    if (agents_per_lane != 0 && agents_per_lane != 1 && agents_per_lane != 2 &&
+        agents_per_lane != 4)
+        return fail(ctx, ORCA_EINVAL, "agents_per_lane must be 0, 1, 2 or 4");
+    if (velocity_waves_per_cu < 1 || velocity_waves_per_cu > 32)
+        return fail(ctx, ORCA_EINVAL, "velocity_waves_per_cu must be in 1..32");
+    if (fallback_work_units != 0 && fallback_work_units != 1)
+        return fail(ctx, ORCA_EINVAL, "fallback_work_units must be 0 or 1");
+    ctx->vel_apl = agents_per_lane;
+    ctx->vel_waves_per_cu = velocity_waves_per_cu;
+    ctx->fb_work_units = fallback_work_units;
     return ORCA_OK;
 }
 

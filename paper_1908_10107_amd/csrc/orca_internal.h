@@ -36,12 +36,14 @@ struct GridDev {
 // every scene plus, with spawning and removal on, one last cell that holds the
 // absent agents (so cell_start of that cell is the number of present agents).
 // step is the step index the next binning evaluates presence at; removed is
-// written on request (the agents whose state is 1).
+// written on request (the agents whose state is 1).  tiles are the per-XCD
+// tile queues of the fused velocity kernel (cleared before every pass).
 struct Counters {
     uint32_t total_cells;
     uint32_t n_fallback;
     int32_t step;
     uint32_t removed;
+    uint32_t tiles[8];
 };
 
 // FallbackItem (the record of an agent whose projection was empty) and the
@@ -89,6 +91,9 @@ struct Plan {
     int32_t n, n_scenes, ld, cus, n_chunks;
     int32_t knn_block;        // threads per k_knn block (64..512)
     int32_t fb_waves_per_cu;  // persistent k_fallback waves per CU
+    int32_t vel_apl;          // 0: k_knn + k_lp; 1, 2, 4: the fused k_velocity, agents per lane
+    int32_t vel_waves_per_cu; // persistent k_velocity waves per CU
+    int32_t fb_work_units;    // 1: k_fallback with work units (K <= 16)
     uint32_t max_cells;
     const int32_t *off;
     const SceneDev *sp;
@@ -116,6 +121,7 @@ hipError_t launch_scene_map(const int32_t *off, int32_t n_scenes, int32_t *agent
 // advance: move the step counter on (a step with spawning and removal)
 hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, bool advance,
                        hipStream_t st);
+// also clears the fallback count and the tile queues for the velocity pass
 hipError_t launch_fill_vel(const Plan &pl, const float *vel, hipStream_t st);
 hipError_t launch_count_removed(const uint8_t *state, int32_t n, Counters *counters,
                                 hipStream_t st);

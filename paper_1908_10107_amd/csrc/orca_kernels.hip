@@ -67,6 +67,21 @@ __device__ __forceinline__ uint32_t wave_reduce_sum_u32(uint32_t v)
     return v;
 }
 
+// Tile of block b of nb.  Workgroups are handed to the 8 XCDs round robin
+// (block b to XCD b mod 8), and each XCD has its own L2; this mapping gives
+// each XCD one contiguous range of tiles, so agents that share neighbours (cell
+// order) meet in the same L2.  A bijection of [0, nb) for any nb.
+#ifndef ORCA_XCD_SWIZZLE
+#define ORCA_XCD_SWIZZLE 1
+#endif
+constexpr int32_t kXcds = 8;
+__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t nb)
+{
+    if (!ORCA_XCD_SWIZZLE) return b;
+    const int32_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds, i = b / kXcds;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Squared distance in float32 with every operation rounded on its own (no
 // fused multiply-add): the neighbour set is decided by this value.
 __device__ __forceinline__ float dist2_f32(float xi, float yi, float xj, float yj)
@@ -220,6 +235,7 @@ __global__ __launch_bounds__(256) void k_grid(int32_t n_scenes, const int32_t *_
         counters->total_cells = base + (life ? 1u : 0u);
         counters->n_fallback = 0;
     }
+    if (threadIdx.x < kXcds) counters->tiles[threadIdx.x] = 0u;
     __syncthreads();
     for (int32_t s = threadIdx.x; s < n_scenes; s += blockDim.x) {
         bbox[4 * s + 0] = 0xffffffffu;
@@ -403,11 +419,16 @@ __global__ __launch_bounds__(256) void k_scatter(const float *__restrict__ pos,
     inv[i] = d;
 }
 
+// Velocities into the sorted copy for a velocity pass on an existing grid;
+// also starts the pass's fallback list and tile queues empty.
 __global__ __launch_bounds__(256) void k_fill_vel(const float *__restrict__ vel, int32_t n,
                                                   const int32_t *__restrict__ inv,
-                                                  float4 *__restrict__ sorted)
+                                                  float4 *__restrict__ sorted,
+                                                  Counters *__restrict__ counters)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) counters->n_fallback = 0;
+    if (i < 8) counters->tiles[i] = 0u;
     if (i >= n) return;
     float2 *dst = reinterpret_cast<float2 *>(&sorted[inv[i]]) + 1;
     *dst = make_float2(vel[i], vel[n + i]);
@@ -474,10 +495,11 @@ __device__ __forceinline__ void knn_run(uint64_t (&best)[KMAX], uint32_t &lim, u
     }
 }
 
-// K nearest of each agent (sorted order s) among the agents of the cells
-// within neighbor_dist, strictly inside it, nearest first, ties by agent id.
-// Writes nbr[k * ld + s] = the neighbour's sorted index, with bit 31 set when
-// the neighbour's id is the smaller of the pair, and ncount[s].
+// The K nearest of one agent (me, id myid, in a scene with grid g, cap K and
+// float32 neighbor_dist^2 nd2) among the agents of the cells within
+// neighbor_dist, strictly inside it, nearest first, ties by agent id, as
+// packed keys in best (see knn_offer).  Returns the number of leading slots
+// that hold the key 0 (KMAX - K; KMAX when K == 0 or nd2 admits nobody).
 //
 // Each row within reach is read over the cells its chord of the disc touches
 // (one contiguous run of sorted indices), own row first.  Cells are about
@@ -485,6 +507,71 @@ __device__ __forceinline__ void knn_run(uint64_t (&best)[KMAX], uint32_t &lim, u
 // once the grid was widened to nd).  The chord is taken a little wider than
 // nd, so rounding of the cell arithmetic or of the float32 distance never
 // drops a neighbour: the distance test decides.
+template <int KMAX>
+__device__ __forceinline__ int32_t knn_search(uint64_t (&best)[KMAX], float4 me, int32_t myid,
+                                              const GridDev &g, int32_t K, float nd2, float ndf,
+                                              const float4 *__restrict__ sorted,
+                                              const int32_t *__restrict__ sid,
+                                              const int32_t *__restrict__ cell_start)
+{
+    // d2 < nd2 as bit patterns: at most the pattern just below nd2's (an nd2
+    // that underflowed to zero admits nobody)
+    if (K == 0 || !(nd2 > 0.0f)) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) best[k] = 0ull;
+        return KMAX;
+    }
+    const int32_t pad = KMAX - K;  // leading slots that hold the key 0
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) best[k] = k < pad ? 0ull : ~0ull;
+    const uint32_t nd_lim = __float_as_uint(nd2) - 1u;
+    uint32_t lim = nd_lim;
+    int32_t cx, cy;  // the agent's cell
+    cell_of(g, me.x, me.y, cx, cy);
+    const double cell = g.cell, nd = (double)ndf;
+    // rows and columns the disc of radius nd can reach: nd / cell rounded up
+    // (cells are a little wider than nd / kCellsPerNd, or wider still once the
+    // grid was widened)
+    const int32_t reach = max(1, min(kCellsPerNd, (int32_t)ceil(nd / cell)));
+    const double px = (double)me.x, py = (double)me.y;
+    const double ndx = nd * (1.0 + 1e-6) + 1e-9 * (1.0 + fabs(px) + fabs(py));
+    for (int32_t q = 0; q <= 2 * reach; ++q) {
+        const int32_t dy = (q & 1) ? -((q + 1) >> 1) : (q >> 1);  // 0, -1, +1, -2, +2
+        const int32_t row = cy + dy;
+        if (row < 0 || row >= g.ny) continue;
+        double dyc = 0.0;  // distance from the agent to the row's band in y
+        if (dy > 0) dyc = fmax(g.y0 + (double)row * cell - py, 0.0);
+        if (dy < 0) dyc = fmax(py - (g.y0 + (double)(row + 1) * cell), 0.0);
+        if (dyc >= ndx) continue;
+        const double hw = sqrt(ndx * ndx - dyc * dyc);
+        const int32_t c0 = max((int32_t)fmax(floor((px - hw - g.x0) / cell), -1.0), max(cx - reach, 0));
+        const int32_t c1 = min((int32_t)fmin(floor((px + hw - g.x0) / cell), (double)g.nx),
+                               min(cx + reach, g.nx - 1));
+        if (c0 > c1) continue;
+        const int32_t rb = g.base + row * g.nx;
+        knn_run<KMAX>(best, lim, nd_lim, me.x, me.y, (uint32_t)myid, cell_start[rb + c0],
+                      cell_start[rb + c1 + 1], sorted, sid);
+    }
+    return pad;
+}
+
+// Neighbour-list entry of slot k of best (pad leading slots): the
+// neighbour's sorted index, with bit 31 set when this agent (id myid) does
+// not come first of the pair (ids order it); -1 for an empty slot.
+template <int KMAX>
+__device__ __forceinline__ int32_t knn_entry(const uint64_t (&best)[KMAX], int k, int32_t pad,
+                                             int32_t myid, const int32_t *__restrict__ inv)
+{
+    if (k < pad || best[k] == ~0ull) return -1;
+    const uint32_t jid = (uint32_t)(best[k] & 0xffffffffu) - 1u;
+    const uint32_t later = (uint32_t)myid < jid ? 0u : 0x80000000u;
+    return (int32_t)((uint32_t)inv[jid] | later);
+}
+
+// K nearest of each agent (sorted order s), as knn_search finds them (the
+// same search, written out: this kernel keeps the registers of six waves per
+// SIMD only in this form).  Writes nbr[k * ld + s] (entries as knn_entry
+// gives them) and ncount[s].
 template <int KMAX>
 __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
                                              const int32_t *__restrict__ sid,
@@ -497,7 +584,7 @@ __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
                                              int32_t *__restrict__ ncount,
                                              Counters *__restrict__ counters, int32_t life)
 {
-    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     // the fallback list of this velocity pass starts empty (k_lp runs after us)
     if (s == 0) counters->n_fallback = 0;
     // absent agents sit in the last cell, after every present one
@@ -608,24 +695,36 @@ struct LpRows<KMAX, false> {
     }
 };
 
-// Load agent s's neighbours and build their half-planes into `rows`.  The
-// neighbour loads are issued G at a time before those half-planes are built,
-// so one memory latency covers each group: two with the rows in registers,
-// which keeps k_lp within the registers of three waves per SIMD (the other
-// waves then cover the latency), eight with the rows in LDS.  Neighbour ids
-// are fetched only when they are written out (the pair order comes with the
-// entry).
-template <int KMAX, class Rows>
-__device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t id, float4 me,
-                                                 const SceneDev &p, const AgentProps &ag,
-                                                 const float4 *__restrict__ sorted,
-                                                 const int32_t *__restrict__ sid,
-                                                 const int32_t *__restrict__ nbr, int32_t ld,
-                                                 const int32_t *__restrict__ ncount,
-                                                 int32_t *__restrict__ nbr_out, int32_t krow)
+// Where build_constraints takes an agent's neighbour entries (sorted index,
+// pair-order bit 31) from: the list k_knn wrote, or registers of the fused
+// velocity kernel (slot k of the unrolled loops: a static index).
+struct EntriesInMemory {
+    const int32_t *__restrict__ nbr;
+    int32_t ld, s;
+    __device__ __forceinline__ int32_t operator()(int k) const { return nbr[(int64_t)k * ld + s]; }
+};
+template <int KMAX>
+struct EntriesInRegs {
+    const int32_t (&e)[KMAX];
+    __device__ __forceinline__ int32_t operator()(int k) const { return e[k]; }
+};
+
+// Load the m neighbours of agent id (state me) and build their half-planes
+// into `rows`.  The neighbour loads are issued G at a time before those
+// half-planes are built, so one memory latency covers each group: two with
+// the rows in registers, which keeps the LP kernels within the registers of
+// three waves per SIMD (the other waves then cover the latency), eight with
+// the rows in LDS.  Neighbour ids are fetched only when they are written out
+// (the pair order comes with the entry).
+template <int KMAX, class Rows, class Src>
+__device__ __forceinline__ void build_constraints(Rows &rows, const Src &src, int m, int32_t id,
+                                                  float4 me, const SceneDev &p,
+                                                  const AgentProps &ag,
+                                                  const float4 *__restrict__ sorted,
+                                                  const int32_t *__restrict__ sid,
+                                                  int32_t *__restrict__ nbr_out, int32_t krow)
 {
     constexpr int G = KMAX <= kLpRegRows ? 2 : 8;
-    const int32_t m = ncount[s];
     // combined radius r_i + r_j (section 4: people of different sizes)
     const double ri = (double)(ag.radius ? ag.radius[id] : p.radius);
     const double tau = (double)p.tau, dt = (double)p.dt;
@@ -637,8 +736,7 @@ __device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t 
         float4 o[G];
         float rj[G];
 #pragma unroll
-        for (int u = 0; u < G; ++u)
-            e[u] = k0 + u < KMAX && k0 + u < m ? nbr[(int64_t)(k0 + u) * ld + s] : 0;
+        for (int u = 0; u < G; ++u) e[u] = k0 + u < KMAX && k0 + u < m ? src(k0 + u) : 0;
 #pragma unroll
         for (int u = 0; u < G; ++u)
             o[u] = k0 + u < KMAX && k0 + u < m ? sorted[e[u] & 0x7fffffff]
@@ -667,7 +765,6 @@ __device__ __forceinline__ int build_constraints(Rows &rows, int32_t s, int32_t 
                 nbr_out[(int64_t)id * krow + k] = k < m ? sid[e[u] & 0x7fffffff] : -1;
         }
     }
-    return m;
 }
 
 __device__ __forceinline__ void preferred_velocity(const SceneDev &p, const AgentProps &ag,
@@ -738,14 +835,106 @@ __device__ __forceinline__ void write_result(const OutArgs &o, float mex, float 
     if (o.status) o.status[id] = status;
 }
 
+// Velocity of agent s (sorted order; state me, id id, its m neighbour
+// entries from src): preferred velocity, half-planes, 2D LP.  A feasible
+// agent gets its result written (and its choice recorded with REC) and false
+// is returned; an agent whose projection is empty gets its fallback record in
+// `it` and true is returned (its rows stay in `rows`).
+template <int KMAX, int MODE, class Src>
+__device__ __forceinline__ bool lp_agent(LpRows<KMAX> &rows, FallbackItem &it, const Src &src,
+                                         int m, int32_t s, float4 me, int32_t id,
+                                         const SceneDev &p, const OutArgs &out, int32_t n,
+                                         const float4 *__restrict__ sorted,
+                                         const int32_t *__restrict__ sid)
+{
+    constexpr bool REC = MODE == kModeRec, LIFE = MODE == kModeLife;
+    double vhx, vhy;
+    preferred_velocity(p, out.ag, me, id, n, out.pref, out.goals, vhx, vhy);
+    const float vmaxf = out.ag.max_speed ? out.ag.max_speed[id] : p.vmax;
+    const double vmax = (double)vmaxf;
+    double vx, vy;
+    disc_clip(vmax, vhx, vhy, vx, vy);
+    build_constraints<KMAX>(rows, src, m, id, me, p, out.ag, sorted, sid, out.nbr_out, out.krow);
+    Active act;
+    const int fail = rows.project(m, vmax, vhx, vhy, vx, vy, &act);
+    if (REC) out.tape_state[s] = me;
+    if (fail < 0) {
+        write_result<LIFE>(out, me.x, me.y, p.dt, id, n, vx, vy, vhx, vhy, 0);
+        if (REC) {
+            TapeCode tc{};
+            tc.status = 0;
+            tc.p_line = (int8_t)act.line;
+            tc.p_src = (int8_t)act.src;
+            tc.d_plane = -1;
+            tc.d_line = (int8_t)kLineNone;
+            tc.d_src = (int8_t)kSrcDisc;
+            out.tape_codes[s] = tc;
+        }
+        return false;
+    }
+    it.s = s;
+    it.id = id;
+    it.m = (int8_t)m;
+    it.fail = (int8_t)fail;
+    it.line = (int8_t)act.line;
+    it.src = (int8_t)act.src;
+    // the most violated row from the failed one on, at the last optimum
+    it.worst = (int8_t)worst_row<KMAX>(rows, fail, m, vx, vy);
+    it.vx = vx;
+    it.vy = vy;
+    it.vhx = vhx;
+    it.vhy = vhy;
+    it.vmax = vmaxf;
+    it.dt = p.dt;
+    it.mex = me.x;
+    it.mey = me.y;
+    return true;
+}
+
+// Hand the wave's infeasible agents to the fallback list (one atomic per
+// wave): each one's record, its sort key (the failed row) and its half-planes
+// in its stash slot, in stash_position order.  Every lane of the wave calls it.
+template <int KMAX>
+__device__ __forceinline__ void append_fallback(bool need_fb, const FallbackItem &it,
+                                                const LpRows<KMAX> &rows,
+                                                FallbackItem *__restrict__ fb_list,
+                                                uint8_t *__restrict__ fb_key, int32_t kcap,
+                                                double2 *__restrict__ stash_n,
+                                                double *__restrict__ stash_b,
+                                                Counters *__restrict__ counters)
+{
+    const uint64_t mask = __ballot(need_fb);
+    if (!mask) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t before = __builtin_amdgcn_mbcnt_hi(
+        (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    uint32_t slot0 = 0;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    if ((int)lane == leader) slot0 = atomicAdd(&counters->n_fallback, (uint32_t)__popcll(mask));
+    slot0 = __shfl(slot0, leader, 64);
+    if (need_fb) {
+        const uint32_t slot = slot0 + before;
+        fb_list[slot] = it;
+        fb_key[slot] = (uint8_t)it.fail;
+        double2 *gn = stash_n + (int64_t)slot * kcap;
+        double *gb = stash_b + (int64_t)slot * kcap;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if (k < it.m) {
+                const int q = stash_position(k, it);
+                gn[q] = rows.N(k);
+                gb[q] = rows.B(k);
+            }
+        }
+    }
+}
+
 // One lane per agent in cell order, half-planes in registers (LDS above 16
 // rows).  With the rows in registers the kernel is held to the registers of
 // three waves per SIMD: it is bound by the latency of its float64 chains and
 // gathers, which a third wave covers better than the unconstrained two (a few
-// bytes of spill).  Feasible agents finish here; an agent whose projection is
-// handed to the fallback list with everything
-// k_fallback needs (one atomic per wave): its record, its sort key (the failed
-// row) and its half-planes in stash slot `slot`, in stash_position order.
+// bytes of spill).  Feasible agents finish here; the others go to the
+// fallback list.
 template <int KMAX, int MODE>
 __global__ __launch_bounds__(kLpBlock)
 __attribute__((amdgpu_waves_per_eu(KMAX <= kLpRegRows ? 3 : 1))) void k_lp(
@@ -756,11 +945,11 @@ __attribute__((amdgpu_waves_per_eu(KMAX <= kLpRegRows ? 3 : 1))) void k_lp(
     double2 *__restrict__ stash_n, double *__restrict__ stash_b, Counters *__restrict__ counters,
     const int32_t *__restrict__ cell_start)
 {
-    constexpr bool REC = MODE == kModeRec, LIFE = MODE == kModeLife;
+    constexpr bool LIFE = MODE == kModeLife;
     constexpr bool kRegs = KMAX <= kLpRegRows;
     __shared__ double2 s_n[kRegs ? 1 : KMAX * kLpBlock];
     __shared__ double s_b[kRegs ? 1 : KMAX * kLpBlock];
-    const int32_t s = blockIdx.x * kLpBlock + threadIdx.x;
+    const int32_t s = xcd_tile(blockIdx.x, gridDim.x) * kLpBlock + threadIdx.x;
     LpRows<KMAX> rows;
     if constexpr (!kRegs) rows.L = Lane{s_n + threadIdx.x, s_b + threadIdx.x};
     bool need_fb = false;
@@ -783,71 +972,88 @@ __attribute__((amdgpu_waves_per_eu(KMAX <= kLpRegRows ? 3 : 1))) void k_lp(
         const float4 me = sorted[s];
         const int32_t id = sid[s];
         const SceneDev p = sp[agent_scene[id]];
-        double vhx, vhy;
-        preferred_velocity(p, out.ag, me, id, n, out.pref, out.goals, vhx, vhy);
-        const float vmaxf = out.ag.max_speed ? out.ag.max_speed[id] : p.vmax;
-        const double vmax = (double)vmaxf;
-        double vx, vy;
-        disc_clip(vmax, vhx, vhy, vx, vy);
-        const int m = build_constraints<KMAX>(rows, s, id, me, p, out.ag, sorted, sid, nbr, ld,
-                                              ncount, out.nbr_out, out.krow);
-        Active act;
-        const int fail = rows.project(m, vmax, vhx, vhy, vx, vy, &act);
-        if (REC) out.tape_state[s] = me;
-        if (fail < 0) {
-            write_result<LIFE>(out, me.x, me.y, p.dt, id, n, vx, vy, vhx, vhy, 0);
-            if (REC) {
-                TapeCode tc{};
-                tc.status = 0;
-                tc.p_line = (int8_t)act.line;
-                tc.p_src = (int8_t)act.src;
-                tc.d_plane = -1;
-                tc.d_line = (int8_t)kLineNone;
-                tc.d_src = (int8_t)kSrcDisc;
-                out.tape_codes[s] = tc;
-            }
-        } else {
-            need_fb = true;
-            it.s = s;
-            it.id = id;
-            it.m = (int8_t)m;
-            it.fail = (int8_t)fail;
-            it.line = (int8_t)act.line;
-            it.src = (int8_t)act.src;
-            // the most violated row from the failed one on, at the last optimum
-            it.worst = (int8_t)worst_row<KMAX>(rows, fail, m, vx, vy);
-            it.vx = vx;
-            it.vy = vy;
-            it.vhx = vhx;
-            it.vhy = vhy;
-            it.vmax = vmaxf;
-            it.dt = p.dt;
-            it.mex = me.x;
-            it.mey = me.y;
-        }
+        need_fb = lp_agent<KMAX, MODE>(rows, it, EntriesInMemory{nbr, ld, s}, ncount[s], s, me,
+                                       id, p, out, n, sorted, sid);
     }
-    const uint64_t mask = __ballot(need_fb);
-    if (mask) {
-        const uint32_t lane = threadIdx.x & 63;
-        const uint32_t before = __builtin_amdgcn_mbcnt_hi(
-            (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        uint32_t slot0 = 0;
-        const int leader = __ffsll((unsigned long long)mask) - 1;
-        if ((int)lane == leader) slot0 = atomicAdd(&counters->n_fallback, (uint32_t)__popcll(mask));
-        slot0 = __shfl(slot0, leader, 64);
-        if (need_fb) {
-            const uint32_t slot = slot0 + before;
-            fb_list[slot] = it;
-            fb_key[slot] = (uint8_t)it.fail;
-            double2 *gn = stash_n + (int64_t)slot * kcap;
-            double *gb = stash_b + (int64_t)slot * kcap;
+    append_fallback<KMAX>(need_fb, it, rows, fb_list, fb_key, kcap, stash_n, stash_b, counters);
+}
+
+// Persistent velocity kernel: the neighbour search, half-planes and 2D LP of
+// each agent in one pass, so its neighbour list never leaves registers (no
+// list written and read back, one launch instead of two).  One-wave blocks
+// take tiles of kLpBlock * APL agents in cell order (each lane APL agents, a
+// wave apart) from queues of tiles, one queue per XCD over one contiguous
+// eighth of the tiles: a block takes from the queue of its own XCD (blocks
+// go to XCDs round robin), so neighbouring tiles share that XCD's L2, and
+// when that queue is empty it takes from the others in turn.  A queue's
+// counter is only ever incremented, and a block leaves once every queue is
+// past its end, so every block exits.  Plain steps only (no recording, no
+// spawning and removal); results equal those of k_knn + k_lp bit for bit.
+template <int KMAX, int APL>
+__global__ __launch_bounds__(kLpBlock)
+__attribute__((amdgpu_waves_per_eu(KMAX <= kLpRegRows ? 3 : 1))) void k_velocity(
+    const float4 *__restrict__ sorted, const int32_t *__restrict__ sid,
+    const int32_t *__restrict__ inv, const int32_t *__restrict__ cell_start,
+    const GridDev *__restrict__ grid, const int32_t *__restrict__ agent_scene,
+    const SceneDev *__restrict__ sp, int32_t n, OutArgs out, FallbackItem *__restrict__ fb_list,
+    uint8_t *__restrict__ fb_key, int32_t kcap, double2 *__restrict__ stash_n,
+    double *__restrict__ stash_b, Counters *__restrict__ counters)
+{
+    constexpr bool kRegs = KMAX <= kLpRegRows;
+    __shared__ double2 s_n[kRegs ? 1 : KMAX * kLpBlock];
+    __shared__ double s_b[kRegs ? 1 : KMAX * kLpBlock];
+    LpRows<KMAX> rows;
+    if constexpr (!kRegs) rows.L = Lane{s_n + threadIdx.x, s_b + threadIdx.x};
+    constexpr int32_t kTile = kLpBlock * APL;
+    const int32_t n_tiles = (n + kTile - 1) / kTile;
+    const int32_t q = n_tiles / kXcds, r = n_tiles % kXcds;
+    const int32_t home = (int32_t)(blockIdx.x % kXcds);
+    for (int32_t v = 0; v < kXcds; ++v) {
+        const int32_t x = (home + v) % kXcds;
+        const int32_t t0 = x * q + min(x, r);
+        const int32_t len = q + (x < r ? 1 : 0);
+        for (;;) {
+            uint32_t t = 0;
+            if (threadIdx.x == 0) t = atomicAdd(&counters->tiles[x], 1u);
+            t = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)t);
+            if (t >= (uint32_t)len) break;
+            const int32_t base = (t0 + (int32_t)t) * kTile;
+#pragma unroll 1
+            for (int32_t a = 0; a < APL; ++a) {
+                const int32_t s = base + a * kLpBlock + (int32_t)threadIdx.x;
+                bool need_fb = false;
+                FallbackItem it{};
+                if (s < n) {
+                    const float4 me = sorted[s];
+                    const int32_t id = sid[s];
+                    const int32_t sc = agent_scene[id];
+                    const SceneDev p = sp[sc];
+                    int32_t e[KMAX];
+                    int m = 0;
+                    {
+                        uint64_t best[KMAX];
+                        const int32_t pad = knn_search<KMAX>(best, me, id, grid[sc], p.k, p.nd2,
+                                                             p.nd, sorted, sid, cell_start);
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                if (k < it.m) {
-                    const int q = stash_position(k, it);
-                    gn[q] = rows.N(k);
-                    gb[q] = rows.B(k);
+                        for (int k = 0; k < KMAX; ++k) {
+                            e[k] = knn_entry<KMAX>(best, k, pad, id, inv);
+                            m += e[k] != -1 ? 1 : 0;
+                        }
+                        // the K nearest sit in the last K slots: move them to
+                        // the front (a shifter over static indices, by pad)
+#pragma unroll
+                        for (int b = 1; b < KMAX; b <<= 1) {
+                            const bool sh = (pad & b) != 0;
+#pragma unroll
+                            for (int k = 0; k < KMAX; ++k)
+                                e[k] = sh ? (k + b < KMAX ? e[k + b] : -1) : e[k];
+                        }
+                    }
+                    need_fb = lp_agent<KMAX, kModePlain>(rows, it, EntriesInRegs<KMAX>{e}, m, s,
+                                                         me, id, p, out, n, sorted, sid);
                 }
+                append_fallback<KMAX>(need_fb, it, rows, fb_list, fb_key, kcap, stash_n, stash_b,
+                                      counters);
             }
         }
     }
@@ -944,18 +1150,266 @@ struct FbRows<KMAX, false> {
     }
 };
 
-// The persistent loop of k_fallback over its share of the sorted list.
-template <int KMAX, int MODE, class RS>
-__device__ __forceinline__ void fallback_items(RS &rows, const OutArgs &out, int32_t n, int32_t kcap,
+// ------------------------------------------------------------------ work units
+//
+// Work units (section 3): the recompute of a new velocity is cut into pieces
+// of equal size that lanes with nothing to recompute take over.  In the
+// fallback the recompute that runs longest is the 1D program on a violated
+// line of a plane subproblem: it visits every earlier row of the lane's own
+// store, so a wave pays for its longest such program while the lanes that
+// have none (or have finished their agent) wait.  With work units, the lanes
+// whose line i is violated (at most kLpBlock / kWuGroup of them) publish the
+// line in LDS; kWuGroup lanes per line each fold an equal, contiguous share
+// of its i + 1 earlier rows (read from the owner's rows in LDS) into a
+// partial interval; the group combines its partials in row order across
+// lanes (the later partial's ends are offered to the earlier one, with the
+// same strict tests as adding a row, so the earliest of equal bounds wins as
+// in the one-lane program); the owner takes the result.  Lines with fewer
+// than kWuFrom earlier rows, or steps where too many lanes recompute at once,
+// run the one-lane program.  Each partial starts from the disc's interval,
+// which is part of every line's program.
+
+constexpr int kWuGroup = 4;  // lanes per published line
+constexpr int kWuFrom = 6;   // fewest earlier rows (i + 1) worth splitting
+constexpr int kWuLines = kLpBlock / kWuGroup;
+
+// LDS of one fallback wave (one-wave blocks): each lane's rows in stash
+// order, and the lines of one step with their combined intervals.
+template <int KB>
+struct WuShared {
+    double nx[KB][kLpBlock], ny[KB][kLpBlock], b[KB][kLpBlock];
+    double line[kWuLines][8];  // mx, my, ci, mm, root, nk.x, nk.y, bk of the owner's line
+    int32_t owner[kWuLines];
+    double res[kWuLines][4];   // lo_n, lo_d, hi_n, hi_d
+    int32_t rsrc[kWuLines][2];
+};
+
+__device__ __forceinline__ void shfl_xor_interval(const Interval &a, Interval &o, int d)
+{
+    o.lo_n = __shfl_xor(a.lo_n, d, 64);
+    o.lo_d = __shfl_xor(a.lo_d, d, 64);
+    o.hi_n = __shfl_xor(a.hi_n, d, 64);
+    o.hi_d = __shfl_xor(a.hi_d, d, 64);
+    o.lo_src = __shfl_xor(a.lo_src, d, 64);
+    o.hi_src = __shfl_xor(a.hi_src, d, 64);
+}
+
+// lp2_plane for a whole wave with work units.  Every lane of the wave calls
+// it (active: the lane has a plane k to solve; the others only help).
+template <int KB, class RS>
+__device__ __forceinline__ bool lp2_plane_wu(const RS &L, WuShared<KB> &W, bool active, int k,
+                                             double2 nk, double bk, double vmax, double &vx,
+                                             double &vy, Active *act)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const double vm2 = vmax * vmax;
+    vx = vmax * nk.x;
+    vy = vmax * nk.y;
+    act->line = kLineNone;
+    act->src = kSrcDisc;
+    bool ok = active;
+#pragma unroll
+    for (int i = -1; i < KB - 1; ++i) {
+        // this lane's step i of the plane program: is line i violated, and
+        // does its 1D program run?
+        bool run = false;
+        double mx = 0.0, my = 0.0, ci = 0.0, mm = 0.0, root = 0.0;
+        if (ok && i < k) {
+            plane_row(L, i, nk, bk, mx, my, ci);
+            if (!(mx * vx + my * vy >= ci)) {
+                mm = mx * mx + my * my;
+                if (mm == 0.0) {
+                    ok = !(ci > 0.0);
+                } else {
+                    const double disc = vm2 * mm - ci * ci;
+                    if (disc < 0.0) {
+                        ok = false;
+                    } else {
+                        root = sqrt(disc);
+                        run = true;
+                    }
+                }
+            }
+        }
+        const uint64_t mask = __ballot(run);
+        if (mask == 0) continue;
+        Interval iv;
+        const int nrun = __popcll(mask);
+        if (i + 1 >= kWuFrom && nrun <= kWuLines) {
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            if (run) {
+                W.owner[rank] = lane;
+                W.line[rank][0] = mx;
+                W.line[rank][1] = my;
+                W.line[rank][2] = ci;
+                W.line[rank][3] = mm;
+                W.line[rank][4] = root;
+                W.line[rank][5] = nk.x;
+                W.line[rank][6] = nk.y;
+                W.line[rank][7] = bk;
+            }
+            // one wave per block: its LDS accesses complete in issue order
+            __builtin_amdgcn_wave_barrier();
+            const int g = lane / kWuGroup, r = lane % kWuGroup;
+            const int per = (i + 1 + kWuGroup - 1) / kWuGroup;  // rows per share
+            Interval part;
+            part.init(1.0, 1.0);
+            if (g < nrun) {
+                const int p = W.owner[g];
+                const double pmx = W.line[g][0], pmy = W.line[g][1], pci = W.line[g][2];
+                const double pmm = W.line[g][3];
+                const double pkx = W.line[g][5], pky = W.line[g][6], pbk = W.line[g][7];
+                part.init(W.line[g][4], pmm);
+#pragma unroll
+                for (int u = 0; u < per; ++u) {
+                    const int j = -1 + r * per + u;
+                    if (j < i) {
+                        double ax, ay, cj;
+                        if (j < 0) {
+                            ax = -pkx;
+                            ay = -pky;
+                            cj = -pbk;
+                        } else {
+                            ax = W.nx[j][p] - pkx;
+                            ay = W.ny[j][p] - pky;
+                            cj = W.b[j][p] - pbk;
+                        }
+                        double den, num;
+                        plane_term(ax, ay, cj, pmx, pmy, pci, pmm, den, num);
+                        part.add(den, num, j);
+                    }
+                }
+            }
+            // combine the group's partials, earlier rows first
+#pragma unroll
+            for (int d = 1; d < kWuGroup; d <<= 1) {
+                Interval o;
+                shfl_xor_interval(part, o, d);
+                if (lane & d) {
+                    o.add(part.lo_d, part.lo_n, part.lo_src);
+                    o.add(part.hi_d, part.hi_n, part.hi_src);
+                    part = o;
+                } else {
+                    part.add(o.lo_d, o.lo_n, o.lo_src);
+                    part.add(o.hi_d, o.hi_n, o.hi_src);
+                }
+            }
+            if (g < nrun && r == 0) {
+                W.res[g][0] = part.lo_n;
+                W.res[g][1] = part.lo_d;
+                W.res[g][2] = part.hi_n;
+                W.res[g][3] = part.hi_d;
+                W.rsrc[g][0] = part.lo_src;
+                W.rsrc[g][1] = part.hi_src;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (run) {
+                iv.lo_n = W.res[rank][0];
+                iv.lo_d = W.res[rank][1];
+                iv.hi_n = W.res[rank][2];
+                iv.hi_d = W.res[rank][3];
+                iv.lo_src = W.rsrc[rank][0];
+                iv.hi_src = W.rsrc[rank][1];
+            }
+            // the next step's writes must not pass this step's reads
+            __builtin_amdgcn_wave_barrier();
+        } else if (run) {
+            iv.init(root, mm);
+            for (int j = -1; j < i; ++j) {
+                double ax, ay, cj;
+                plane_row(L, j, nk, bk, ax, ay, cj);
+                double den, num;
+                plane_term(ax, ay, cj, mx, my, ci, mm, den, num);
+                iv.add(den, num, j);
+            }
+        }
+        if (run) {
+            if (iv.empty()) {
+                ok = false;
+                continue;
+            }
+            plane_point(iv, nk, mx, my, ci, mm, vx, vy, act);
+            act->line = i;
+        }
+    }
+    return ok;
+}
+
+// lp3_least_penetration with every lane staying in the pass loop while any
+// lane still has a plane to take, so the lanes that are done help the others
+// (lp2_plane_wu).  The same passes, planes and arithmetic otherwise.
+template <int KB, class RS>
+__device__ __forceinline__ double lp3_least_penetration_wu(const RS &L, WuShared<KB> &W, int m,
+                                                           int start, double vmax, double &vx,
+                                                           double &vy, int *plane, Active *act)
+{
+    double t = 0.0;
+    *plane = -1;
+    act->line = kLineNone;
+    act->src = kSrcDisc;
+    uint32_t left = rows_below(m) & ~rows_below(start);
+#pragma unroll 1
+    for (int pass = 0; pass < KB; ++pass) {
+        int k = KB;
+        for (int u = KB - 1; u >= 0; --u) {
+            const double2 nu = L.N(u);
+            const bool hit = ((left >> u) & 1u) != 0u && !(nu.x * vx + nu.y * vy + t >= L.B(u));
+            k = hit ? u : k;
+        }
+        const bool active = k < KB;
+        if (__ballot(active) == 0) break;
+        if (active) left &= ~rows_below(k + 1);
+        const int kk = active ? k : 0;
+        const double2 nk = L.NL(kk);
+        const double bk = L.BL(kk);
+        double wx, wy;
+        Active pa;
+        const bool okp = lp2_plane_wu<KB>(L, W, active, k, nk, bk, vmax, wx, wy, &pa);
+        if (active && okp) {
+            vx = wx;
+            vy = wy;
+            t = fmax(bk - (nk.x * vx + nk.y * vy), 0.0);
+            *plane = k;
+            *act = pa;
+        }
+    }
+    return t;
+}
+
+template <int KB>
+struct Lp3WorkUnits {
+    WuShared<KB> *W;
+    template <int KB2, class RS>
+    __device__ __forceinline__ double run(const RS &L, int m, int start, double vmax, double &vx,
+                                          double &vy, int *plane, Active *act) const
+    {
+        return lp3_least_penetration_wu<KB2>(L, *W, m, start, vmax, vx, vy, plane, act);
+    }
+};
+
+// The persistent loop of k_fallback over its share of the sorted list.  With
+// work units (WU) the loop runs in whole-wave rounds (a lane past the end of
+// the list has no agent but stays to help) and each lane's rows also go to
+// LDS for its helpers.
+template <int KMAX, int MODE, bool WU, class RS>
+__device__ __forceinline__ void fallback_items(RS &rows, WuShared<KMAX> *W, const OutArgs &out,
+                                               int32_t n, int32_t kcap,
                                                const FallbackItem *__restrict__ fb_list,
                                                const int32_t *__restrict__ fb_order,
                                                const double2 *__restrict__ stash_n,
                                                const double *__restrict__ stash_b, uint32_t count)
 {
-    for (uint32_t q = blockIdx.x * kLpBlock + threadIdx.x; q < count; q += gridDim.x * kLpBlock) {
-        const int32_t slot = fb_order[q];
-        const FallbackItem it = fb_list[slot];
-        const int m = it.m, fail = it.fail;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t stride = gridDim.x * kLpBlock;
+    for (uint32_t base = blockIdx.x * kLpBlock; WU ? base < count : base + lane < count;
+         base += stride) {
+        const uint32_t q = base + lane;
+        const bool have = q < count;
+        const int32_t slot = have ? fb_order[q] : 0;
+        FallbackItem it{};
+        if (have) it = fb_list[slot];
+        const int m = have ? it.m : 0, fail = have ? it.fail : 0;
         const double2 *gn = stash_n + (int64_t)slot * kcap;
         const double *gb = stash_b + (int64_t)slot * kcap;
         rows.slot(gn, gb);
@@ -968,8 +1422,24 @@ __device__ __forceinline__ void fallback_items(RS &rows, const OutArgs &out, int
         int plane = -1;
         Active dact, ract;
         bool ok;
-        const double d = fallback_velocity<KMAX>(rows, m, fail, (double)it.vmax, it.vhx, it.vhy,
-                                                 vx, vy, &plane, &dact, &ract, &ok);
+        double d;
+        if constexpr (WU) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                const double2 nk = rows.N(k);
+                W->nx[k][lane] = nk.x;
+                W->ny[k][lane] = nk.y;
+                W->b[k][lane] = rows.B(k);
+            }
+            __builtin_amdgcn_wave_barrier();
+            d = fallback_velocity<KMAX>(rows, m, fail, (double)it.vmax, it.vhx, it.vhy, vx, vy,
+                                        &plane, &dact, &ract, &ok, Lp3WorkUnits<KMAX>{W});
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            d = fallback_velocity<KMAX>(rows, m, fail, (double)it.vmax, it.vhx, it.vhy, vx, vy,
+                                        &plane, &dact, &ract, &ok);
+        }
+        if (!have) continue;
         if (MODE == kModeRec) {
             TapeCode tc{};
             tc.status = 1;
@@ -992,8 +1462,9 @@ __device__ __forceinline__ void fallback_items(RS &rows, const OutArgs &out, int
 // before the failed one hold there with t = 0), then the point closest to
 // vhat among those within d* + delta of every half-plane, with the rows that
 // fix d* taken first: the relaxed projection's optimum lies where they cross,
-// so the other rows are rarely violated.
-template <int KMAX, int MODE>
+// so the other rows are rarely violated.  WU: the least-penetration program
+// with work units (rows in registers only, K <= 16).
+template <int KMAX, int MODE, bool WU>
 __global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, int32_t kcap,
                                                        const FallbackItem *__restrict__ fb_list,
                                                        const int32_t *__restrict__ fb_order,
@@ -1002,16 +1473,20 @@ __global__ __launch_bounds__(kLpBlock) void k_fallback(OutArgs out, int32_t n, i
                                                        const Counters *__restrict__ counters)
 {
     constexpr bool kRegs = KMAX <= kLpRegRows;
+    static_assert(!WU || kRegs, "work units serve the register-row fallback");
     __shared__ double2 s_n[kRegs ? 1 : KMAX * kLpBlock];
     __shared__ double s_b[kRegs ? 1 : KMAX * kLpBlock];
+    __shared__ WuShared<WU ? KMAX : 1> s_wu;
     const uint32_t count = counters->n_fallback;
     double rnx[kRegs ? KMAX : 1], rny[kRegs ? KMAX : 1], rb[kRegs ? KMAX : 1];
     if constexpr (kRegs) {
         FbRows<KMAX> rows{rnx, rny, rb, nullptr, nullptr};
-        fallback_items<KMAX, MODE>(rows, out, n, kcap, fb_list, fb_order, stash_n, stash_b, count);
+        fallback_items<KMAX, MODE, WU>(rows, (WuShared<KMAX> *)&s_wu, out, n, kcap, fb_list,
+                                       fb_order, stash_n, stash_b, count);
     } else {
         FbRows<KMAX> rows{Lane{s_n + threadIdx.x, s_b + threadIdx.x}};
-        fallback_items<KMAX, MODE>(rows, out, n, kcap, fb_list, fb_order, stash_n, stash_b, count);
+        fallback_items<KMAX, MODE, false>(rows, (WuShared<KMAX> *)nullptr, out, n, kcap, fb_list,
+                                          fb_order, stash_n, stash_b, count);
     }
 }
 
@@ -1030,9 +1505,20 @@ __global__ __launch_bounds__(256) void k_count_removed(const uint8_t *__restrict
 
 // ------------------------------------------------------------------ launchers
 
+// Recording (for the adjoint) and spawning / removal are separate
+// instantiations: the plain one carries none of their bookkeeping.
+inline int plan_mode(const Plan &pl)
+{
+    return pl.out.tape_codes ? kModeRec : (pl.out.life.spawn_step ? kModeLife : kModePlain);
+}
+
+// The fused velocity kernel serves plain passes when it is selected.
+inline bool plan_fused(const Plan &pl) { return pl.vel_apl > 0 && plan_mode(pl) == kModePlain; }
+
 template <int KMAX>
 hipError_t launch_knn_k(const Plan &pl, hipStream_t st)
 {
+    if (plan_fused(pl)) return hipSuccess;  // k_velocity searches the neighbours itself
     const int32_t n = pl.n;
     const int32_t bs = pl.knn_block;
     hipLaunchKernelGGL(k_knn<KMAX>, dim3((n + bs - 1) / bs), dim3(bs), 0, st, pl.sorted, pl.sid,
@@ -1060,21 +1546,42 @@ hipError_t launch_fallback_mode(const Plan &pl, hipStream_t st)
     hipLaunchKernelGGL(k_fb_sort, dim3(gs), dim3(kFbSortBlock), 0, st, pl.fb_key, pl.fb_order,
                        pl.counters);
     const int32_t gf = max(1, min((pl.n + kLpBlock - 1) / kLpBlock, pl.fb_waves_per_cu * pl.cus));
-    hipLaunchKernelGGL((k_fallback<KMAX, MODE>), dim3(gf), dim3(kLpBlock), 0, st, pl.out, pl.n,
-                       pl.kcap, pl.fb_list, pl.fb_order, pl.stash_n, pl.stash_b, pl.counters);
+    if (pl.fb_work_units && KMAX <= kLpRegRows)
+        hipLaunchKernelGGL((k_fallback<KMAX, MODE, KMAX <= kLpRegRows>), dim3(gf), dim3(kLpBlock),
+                           0, st, pl.out, pl.n, pl.kcap, pl.fb_list, pl.fb_order, pl.stash_n,
+                           pl.stash_b, pl.counters);
+    else
+        hipLaunchKernelGGL((k_fallback<KMAX, MODE, false>), dim3(gf), dim3(kLpBlock), 0, st,
+                           pl.out, pl.n, pl.kcap, pl.fb_list, pl.fb_order, pl.stash_n, pl.stash_b,
+                           pl.counters);
     return hipGetLastError();
 }
 
-// Recording (for the adjoint) and spawning / removal are separate
-// instantiations: the plain one carries none of their bookkeeping.
-inline int plan_mode(const Plan &pl)
+template <int KMAX, int APL>
+hipError_t launch_velocity_apl(const Plan &pl, hipStream_t st)
 {
-    return pl.out.tape_codes ? kModeRec : (pl.out.life.spawn_step ? kModeLife : kModePlain);
+    // persistent: vel_waves_per_cu one-wave blocks per CU, a multiple of the
+    // XCD count so every XCD's queue has its share of blocks
+    constexpr int32_t kTile = kLpBlock * APL;
+    const int32_t tiles = (pl.n + kTile - 1) / kTile;
+    int32_t g = min(pl.vel_waves_per_cu * pl.cus, tiles);
+    g = max(kXcds, (g + kXcds - 1) / kXcds * kXcds);
+    hipLaunchKernelGGL((k_velocity<KMAX, APL>), dim3(g), dim3(kLpBlock), 0, st, pl.sorted, pl.sid,
+                       pl.inv, pl.cell_start, pl.grid, pl.agent_scene, pl.sp, pl.n, pl.out,
+                       pl.fb_list, pl.fb_key, pl.kcap, pl.stash_n, pl.stash_b, pl.counters);
+    return hipGetLastError();
 }
 
 template <int KMAX>
 hipError_t launch_lp_k(const Plan &pl, hipStream_t st)
 {
+    if (plan_fused(pl)) {
+        switch (pl.vel_apl) {
+        case 1: return launch_velocity_apl<KMAX, 1>(pl, st);
+        case 2: return launch_velocity_apl<KMAX, 2>(pl, st);
+        default: return launch_velocity_apl<KMAX, 4>(pl, st);
+        }
+    }
     switch (plan_mode(pl)) {
     case kModeRec: return launch_lp_mode<KMAX, kModeRec>(pl, st);
     case kModeLife: return launch_lp_mode<KMAX, kModeLife>(pl, st);
@@ -1156,7 +1663,7 @@ hipError_t launch_fill_vel(const Plan &pl, const float *vel, hipStream_t st)
 {
     if (pl.n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_vel, dim3((pl.n + 255) / 256), dim3(256), 0, st, vel, pl.n, pl.inv,
-                       pl.sorted);
+                       pl.sorted, pl.counters);
     return hipGetLastError();
 }
 

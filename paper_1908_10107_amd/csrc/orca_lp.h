@@ -411,6 +411,43 @@ ORCA_HDI inline void plane_row(const RS &L, int i, double2 nk, double bk, double
     }
 }
 
+// The term row (ax, ay, cj) adds to the 1D program on projected line
+// (mx, my, ci) with |m|^2 = mm: s (a.d) mm >= c_j mm - c_i (a.m), with
+// d = (-my, mx).  Shared by the plane program and its work-unit form, so both
+// round alike.
+ORCA_HDI inline void plane_term(double ax, double ay, double cj, double mx, double my, double ci,
+                                double mm, double &den, double &num)
+{
+    den = (ay * mx - ax * my) * mm;
+    num = cj * mm - ci * (ax * mx + ay * my);
+}
+
+// Optimum of n_k . v on the projected line (mx, my, ci) within the
+// interval iv of its 1D program; act->src gets what bounds it.
+ORCA_HDI inline void plane_point(const Interval &iv, double2 nk, double mx, double my, double ci,
+                                 double mm, double &vx, double &vy, Active *act)
+{
+    const double slope = nk.y * mx - nk.x * my;  // n_k . (-my, mx)
+    double sn, sd;
+    int src;
+    if (slope > 0.0) {
+        sn = iv.hi_n;
+        sd = iv.hi_d;
+        src = iv.hi_src;
+    } else if (slope < 0.0) {
+        sn = iv.lo_n;
+        sd = iv.lo_d;
+        src = iv.lo_src;
+    } else {
+        src = iv.clamp(0.0, 1.0, sn, sd);
+    }
+    const double s = sn / sd;
+    const double c0 = ci / mm;
+    vx = c0 * mx - s * my;
+    vy = c0 * my + s * mx;
+    act->src = src;
+}
+
 // Maximise n_k . v over the disc and the projected constraints -1..k-1
 // (incremental, as lp2_project but with a linear objective).  Line i is
 // p(s) = c_i m_i / |m_i|^2 + s (-m_i.y, m_i.x); each constraint j on it is
@@ -453,32 +490,16 @@ ORCA_HDI inline bool lp2_plane(const RS &L, int k, double2 nk, double bk, double
             plane_row(L, j, nk, bk, ax, ay, cj);
             ORCA_COUNT(plane_inner);
             // a.(c_i m / mm + s d) >= c_j  ->  s (a.d) mm >= c_j mm - c_i (a.m)
-            iv.add((ay * mx - ax * my) * mm, cj * mm - ci * (ax * mx + ay * my), j);
+            double den, num;
+            plane_term(ax, ay, cj, mx, my, ci, mm, den, num);
+            iv.add(den, num, j);
         }
         if (iv.empty()) {
             ok = false;
             continue;
         }
-        const double slope = nk.y * mx - nk.x * my;  // n_k . (-my, mx)
-        double sn, sd;
-        int src;
-        if (slope > 0.0) {
-            sn = iv.hi_n;
-            sd = iv.hi_d;
-            src = iv.hi_src;
-        } else if (slope < 0.0) {
-            sn = iv.lo_n;
-            sd = iv.lo_d;
-            src = iv.lo_src;
-        } else {
-            src = iv.clamp(0.0, 1.0, sn, sd);
-        }
-        const double s = sn / sd;
-        const double c0 = ci / mm;
-        vx = c0 * mx - s * my;
-        vy = c0 * my + s * mx;
+        plane_point(iv, nk, mx, my, ci, mm, vx, vy, act);
         act->line = i;
-        act->src = src;
     }
     return ok;
 }
@@ -657,12 +678,23 @@ ORCA_HDI inline int worst_row(const RS &rows, int fail, int m, double vx, double
 // d*; *relaxed_ok is false when the relaxed projection was empty (the
 // least-penetration point stands).  plane, dact, ract: what fixed the two
 // programs' optima, rows named by stash position.
-template <int KB, class RS>
+// The least-penetration program fallback_velocity runs by default.
+struct Lp3Plain {
+    template <int KB, class RS>
+    ORCA_HDI double run(const RS &L, int m, int start, double vmax, double &vx, double &vy,
+                        int *plane, Active *act) const
+    {
+        return lp3_least_penetration<KB>(L, m, start, vmax, vx, vy, plane, act);
+    }
+};
+
+template <int KB, class RS, class LP3 = Lp3Plain>
 ORCA_HDI inline double fallback_velocity(const RS &rows, int m, int fail, double vmax, double vhx,
                                          double vhy, double &vx, double &vy, int *plane,
-                                         Active *dact, Active *ract, bool *relaxed_ok)
+                                         Active *dact, Active *ract, bool *relaxed_ok,
+                                         const LP3 &lp3 = LP3())
 {
-    const double d = lp3_least_penetration<KB>(rows, m, fail, vmax, vx, vy, plane, dact);
+    const double d = lp3.template run<KB>(rows, m, fail, vmax, vx, vy, plane, dact);
     FrontRows F;
     F.pos[0] = *plane;
     F.pos[1] = dact->line;

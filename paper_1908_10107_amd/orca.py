@@ -82,6 +82,8 @@ def load(path: str = LIB_PATH):
     L.orca_autotune.restype = ctypes.c_int
     L.orca_set_launch.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
     L.orca_set_launch.restype = ctypes.c_int
+    L.orca_set_kernels.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.orca_set_kernels.restype = ctypes.c_int
     L.orca_set_agents.argtypes = [_P, _P, _P, _P]
     L.orca_set_agents.restype = ctypes.c_int
     L.orca_set_lifecycle.argtypes = [_P, _P, _P, ctypes.c_int32]
@@ -207,16 +209,18 @@ class Context:
                                              _dev_ptr(goals, "goals", n), int(n_steps)))
 
     def autotune(self, pos, vel, pref_vel=None, goals=None, reps=3):
-        """Pick launch shapes on the current grid; returns (knn_block, fallback_waves_per_cu)."""
+        """Pick launch shapes on the current grid; returns (knn_block,
+        fallback_waves_per_cu, agents_per_lane (0: split velocity kernels),
+        velocity_waves_per_cu, fallback_work_units)."""
         n = pos.shape[1]
         scratch = self._torch.empty_like(pos)
-        choice = (ctypes.c_int32 * 2)()
+        choice = (ctypes.c_int32 * 5)()
         self._sync_stream()
         self._check(self.lib.orca_autotune(self.h, _dev_ptr(pos, "pos", n), _dev_ptr(vel, "vel", n),
                                            _dev_ptr(pref_vel, "pref_vel", n),
                                            _dev_ptr(goals, "goals", n), _dev_ptr(scratch, "new_vel", n),
                                            int(reps), choice))
-        return choice[0], choice[1]
+        return tuple(choice)
 
     def set_agents(self, radius=None, max_speed=None, pref_speed=None):
         """Per-agent radius / max speed / walking speed ([N] float32 CUDA tensors, each
@@ -264,6 +268,14 @@ class Context:
     def set_launch(self, knn_block, fallback_waves_per_cu):
         """Fix the launch shapes that autotune would pick (see orca_set_launch)."""
         self._check(self.lib.orca_set_launch(self.h, int(knn_block), int(fallback_waves_per_cu)))
+
+    def set_kernels(self, agents_per_lane=0, velocity_waves_per_cu=12, fallback_work_units=0):
+        """Kernel variants (see orca_set_kernels): agents_per_lane 0 = split
+        neighbour and LP kernels, 1/2/4 = the fused persistent velocity kernel;
+        fallback_work_units 1 = the fallback with work units."""
+        self._check(self.lib.orca_set_kernels(self.h, int(agents_per_lane),
+                                              int(velocity_waves_per_cu),
+                                              int(fallback_work_units)))
 
     def backward(self, tape_step, g_pos_next, g_vel_next, g_pos, g_vel, g_pref_vel,
                  g_max_speed=None, g_time_horizon=None):
