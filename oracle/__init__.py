@@ -301,8 +301,8 @@ def _grad_lib():
         L.oracle_step_jvp.restype = None
         L.oracle_choice_jvp.argtypes = [ctypes.c_int] + [P] * 6 + [F64] * 13 + [P]
         L.oracle_choice_jvp.restype = ctypes.c_int
-        L.oracle_traj_curve.argtypes = [I64, P, P, P, I32, P, P, P, P, I32, P, P, P, P, P, P, P,
-                                        P]
+        L.oracle_traj_curve.argtypes = [I64, P, P, P, I32, P, P, P, P, I32, P, P, P, P, I32, P,
+                                        P, P, P]
         L.oracle_traj_curve.restype = None
         L._grad_ready = True
     return L
@@ -363,12 +363,13 @@ def step_jvp(pos, vel, pref, offsets, params, dpos, dvel, dpref, dvmax, dtau, ra
 
 
 def traj_curve(pos0, vel0, pref, offsets, params, vmax, tau, n_steps, targets, dpref=None,
-               dvmax=None, dtau=None, radius=None, max_speed=None):
+               dvmax=None, dtau=None, radius=None, max_speed=None, f32_state=False):
     """A float64 trajectory step by step: (loss after each step [n_steps],
     directional derivative of that loss along (dpref, dvmax, dtau) [n_steps]
     (zeros without a tangent), hash of each step's discrete decisions
     [n_steps] uint64).  With a tangent the run is a complex step; the
-    decisions are the primal's either way."""
+    decisions are the primal's either way.  f32_state rounds the primal state
+    to float32 after every step."""
     pos0, vel0, pref, targets, vmax, tau, dpref, dvmax, dtau = map(
         _f64, (pos0, vel0, pref, targets, vmax, tau, dpref, dvmax, dtau))
     ag, keep = _agents(radius, max_speed, None)
@@ -379,6 +380,6 @@ def traj_curve(pos0, vel0, pref, offsets, params, vmax, tau, n_steps, targets, d
     _grad_lib().oracle_traj_curve(n, _ptr(pos0), _ptr(vel0), _ptr(pref), len(params),
                                   _ptr(_offsets(offsets, n, len(params))), params_array(params),
                                   _ptr(vmax), _ptr(tau), int(n_steps), _ptr(targets),
-                                  _ptr(dpref), _ptr(dvmax), _ptr(dtau), ag, _ptr(loss),
-                                  _ptr(dloss), _ptr(tape))
+                                  _ptr(dpref), _ptr(dvmax), _ptr(dtau), int(bool(f32_state)),
+                                  ag, _ptr(loss), _ptr(dloss), _ptr(tape))
     return loss, dloss, tape

@@ -778,15 +778,17 @@ void oracle_step_jvp(int64_t n, const float *pos, const float *vel, const float 
  * tape_t[t] = the hash of every decision step t took (in agent order).  With
  * a tangent (dpref, dvmax, dtau, any of them non-NULL) the trajectory runs by
  * complex step and dloss_t[t] is the loss's directional derivative after
- * t + 1 steps along that tangent; the decisions are the primal's.  Used to
+ * t + 1 steps along that tangent; the decisions are the primal's.  With
+ * f32_state the primal state is rounded to float32 after every step, as in
+ * oracle_traj_jvp (the trajectory a float32-state step takes).  Used to
  * count central differences only where no decision switches.
  */
 void oracle_traj_curve(int64_t n, const double *pos0, const double *vel0, const double *pref,
                        int32_t n_scenes, const int64_t *off, const oracle_params *par,
                        const double *vmax_s, const double *tau_s, int32_t n_steps,
                        const double *targets, const double *dpref, const double *dvmax,
-                       const double *dtau, const oracle_agents *ag, double *loss_t,
-                       double *dloss_t, uint64_t *tape_t)
+                       const double *dtau, int32_t f32_state, const oracle_agents *ag,
+                       double *loss_t, double *dloss_t, uint64_t *tape_t)
 {
     uint64_t *ah = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
     const int tangent = dpref || dvmax || dtau;
@@ -797,6 +799,11 @@ void oracle_traj_curve(int64_t n, const double *pos0, const double *vel0, const 
         memcpy(vel, vel0, sizeof(double) * 2 * (size_t)n);
         for (int32_t t = 0; t < n_steps; ++t) {
             traj_step_d(n, pos, vel, pref, n_scenes, off, par, vmax_s, tau_s, ag, ah);
+            if (f32_state)
+                for (int64_t i = 0; i < 2 * n; ++i) {
+                    pos[i] = (double)(float)pos[i];
+                    vel[i] = (double)(float)vel[i];
+                }
             /* summed in long double: central differences divide the loss's
              * rounding by 2h, so it must stay far below L */
             long double L = 0.0L;
@@ -832,6 +839,11 @@ void oracle_traj_curve(int64_t n, const double *pos0, const double *vel0, const 
     }
     for (int32_t t = 0; t < n_steps; ++t) {
         traj_step_c(n, pos, vel, pr, n_scenes, off, par, vm, ta, ag, ah);
+        if (f32_state)
+            for (int64_t i = 0; i < 2 * n; ++i) {
+                pos[i] = (double)(float)creal(pos[i]) + I * cimag(pos[i]);
+                vel[i] = (double)(float)creal(vel[i]) + I * cimag(vel[i]);
+            }
         /* L and its tangent 2 e . e' summed in long double, as above */
         long double Lr = 0.0L, Li = 0.0L;
         for (int64_t i = 0; i < 2 * n; ++i) {

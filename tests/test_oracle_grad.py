@@ -136,3 +136,39 @@ def test_f32_state_jvp(oracle_lib, seed):
         assert abs(dL32 - dL64) <= 1e-5 * size, (d, dL32, dL64, size)
         assert abs(dL32 - fd1) <= 1e-3 * max(1.0, abs(fd1)), (d, dL32, fd1)
     assert counted >= 3
+
+
+def test_f32_state_curve(oracle_lib):
+    """The float32-state branch of the per-step trajectory curve: after each
+    step its loss equals that of the float32 stepper the step parity uses
+    (a separate driver, one step at a time), its tangent equals the
+    float32-state trajectory derivative, and its decision hashes equal the
+    float64 curve's while the two paths take the same decisions (the first
+    step always does: both start from the same state)."""
+    w = small_grad_scene(330)
+    rng = np.random.default_rng(50)
+    steps = 5
+    p = w.params[0]
+    vmax = np.array([np.float32(p.max_speed)], float)
+    tau = np.array([np.float32(p.time_horizon)], float)
+    pos0, vel0 = w.pos.astype(np.float64), w.vel.astype(np.float64)
+    pref = w.pref_vel.astype(np.float64)
+    dp = rng.normal(size=pref.shape)
+    L, dL, tape32 = oracle_lib.traj_curve(pos0, vel0, pref, w.offsets, w.params, vmax, tau, steps,
+                                          w.targets, dpref=dp, dvmax=np.zeros(1),
+                                          dtau=np.zeros(1), f32_state=True)
+    Lp, _, tape32p = oracle_lib.traj_curve(pos0, vel0, pref, w.offsets, w.params, vmax, tau,
+                                           steps, w.targets, f32_state=True)
+    _, _, tape64 = oracle_lib.traj_curve(pos0, vel0, pref, w.offsets, w.params, vmax, tau, steps,
+                                         w.targets)
+    assert np.array_equal(tape32, tape32p)      # the tangent run takes the primal's decisions
+    assert np.allclose(L, Lp, rtol=1e-12, atol=0)
+    assert tape32[0] == tape64[0]
+    x, v = w.pos, w.vel
+    for t in range(steps):
+        x, v, _, _ = oracle_lib.step(x, v, w.pref_vel, w.offsets, w.params)
+        want = float(((x.astype(np.float64) - w.targets) ** 2).sum())
+        assert abs(L[t] - want) <= 1e-12 * abs(want), (t, L[t], want)
+    _, dL_jvp = oracle_lib.traj_jvp(pos0, vel0, pref, w.offsets, w.params, vmax, tau, steps,
+                                    w.targets, dp, np.zeros(1), np.zeros(1), f32_state=True)
+    assert abs(dL[-1] - dL_jvp) <= 1e-9 * max(1.0, abs(dL_jvp))
