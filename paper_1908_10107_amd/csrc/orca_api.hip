@@ -48,6 +48,12 @@ struct orca_ctx {
     double2 *stash_n = nullptr;
     double *stash_b = nullptr;
     float *srad = nullptr;  // per-agent radii in cell order
+    // resident steps (the inner steps of one orca_step call): the state in
+    // cell order, a second id buffer and two buffers of goals or preferred
+    // velocities in cell order (each step reads one, writes the other)
+    float4 *nxt = nullptr;
+    int32_t *sid2 = nullptr;
+    float2 *sg[2] = {nullptr, nullptr};
     std::vector<void *> allocs;
 
     // optional per-agent properties (caller's device arrays), see orca_set_agents
@@ -410,6 +416,10 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->stash_n, sizeof(double2) * A * (size_t)k_max) &&
               alloc((void **)&ctx->stash_b, sizeof(double) * A * (size_t)k_max) &&
               alloc((void **)&ctx->srad, sizeof(float) * A) &&
+              alloc((void **)&ctx->nxt, sizeof(float4) * A) &&
+              alloc((void **)&ctx->sid2, sizeof(int32_t) * A) &&
+              alloc((void **)&ctx->sg[0], sizeof(float2) * A) &&
+              alloc((void **)&ctx->sg[1], sizeof(float2) * A) &&
               alloc((void **)&ctx->acc, sizeof(double) * 4 * A) &&
               alloc((void **)&ctx->acc_scene, sizeof(double) * 2 * S);
     const size_t T = (size_t)tape_steps;
@@ -575,7 +585,25 @@ int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
     pl.out.goals = goals;
     ctx->grid_valid = false;
     if (save_tape) ctx->tape_len = 0;
+    // Plain steps of a multi-step call keep the state in cell order between
+    // steps (resident): only the first step reads and only the last writes
+    // the caller's arrays in agent order.  Results are the same bit for bit
+    // (nothing depends on the order within a cell).  The buffers alternate so
+    // that the last step's ids are in ctx->sid.
+    const bool resident = n_steps > 1 && !save_tape && !ctx->l_spawn;
     for (int32_t t = 0; t < n_steps; ++t) {
+        if (resident) {
+            const int cur = (n_steps - 1 - t) & 1;
+            const bool in = t > 0, out = t < n_steps - 1;
+            pl.sid = cur == 0 ? ctx->sid : ctx->sid2;
+            pl.sid_prev = in ? (cur == 0 ? ctx->sid2 : ctx->sid) : nullptr;
+            pl.res_src = in ? ctx->nxt : nullptr;
+            pl.sg_cur = ctx->sg[cur];
+            pl.sg_prev = in ? ctx->sg[cur ^ 1] : nullptr;
+            pl.sg_src = in ? nullptr : (goals ? goals : pref_vel);
+            pl.out.sg = ctx->sg[cur];
+            pl.out.nxt = out ? ctx->nxt : nullptr;
+        }
         if (save_tape) {
             // the step's neighbour lists and cell-order ids go straight to
             // the tape slot; state and choices are written by sorted index

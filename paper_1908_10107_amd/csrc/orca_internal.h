@@ -84,6 +84,11 @@ struct OutArgs {
     TapeCode *tape_codes;  // recorded step: how each velocity was chosen, by sorted index
     AgentProps ag;         // per-agent properties of this pass
     LifeArgs life;         // spawning and removal (life.spawn_step == nullptr: off)
+    // Resident steps (the inner steps of a multi-step call): the new state
+    // goes to nxt by sorted index instead of the caller's arrays, and the
+    // goal (goals given) or preferred velocity is read from sg by sorted index.
+    float4 *nxt;           // [ld] (x', y', vx', vy') or nullptr
+    const float2 *sg;      // [ld] or nullptr
 };
 
 // Device buffers and sizes of one launch sequence.
@@ -113,6 +118,16 @@ struct Plan {
     int32_t *fb_order; // [ld] fallback slots, sorted by fb_key within chunks of kFbSortChunk
     double2 *stash_n;  // [ld, kcap] half-plane normals of fallback slots, one slot contiguous
     double *stash_b;   // [ld, kcap] half-plane offsets
+    // Binning of a resident step reads the state the previous step left in
+    // cell order (res_src by that step's sorted index, ids in sid_prev, goals
+    // or preferred velocities in sg_prev) instead of the caller's arrays;
+    // otherwise sg_src (the caller's goals or preferred velocities, [2, N]),
+    // when given, is copied into cell order.  The copy goes to sg_cur.
+    const float4 *res_src;
+    const int32_t *sid_prev;
+    const float2 *sg_prev;
+    const float *sg_src;
+    float2 *sg_cur;
     OutArgs out;
 };
 

@@ -125,7 +125,10 @@ __global__ void k_reset_bbox(uint32_t *__restrict__ bbox, int32_t n_scenes)
 // costs 128 x 4 atomics instead of one set per 256 agents.  Blocks of 1024
 // threads keep more of a chunk's loads in flight than 256 (few chunks, so few
 // blocks).
+// pos4 (resident steps): the positions in the previous step's cell order,
+// whose scenes occupy the same index ranges as in agent order.
 __global__ __launch_bounds__(kBboxBlock) void k_bbox(const float *__restrict__ pos, int32_t n,
+                                              const float4 *__restrict__ pos4,
                                               const int2 *__restrict__ chunks,
                                               const int32_t *__restrict__ off,
                                               uint32_t *__restrict__ bbox)
@@ -135,8 +138,17 @@ __global__ __launch_bounds__(kBboxBlock) void k_bbox(const float *__restrict__ p
     const int32_t end = min(ch.y + kBboxChunk, off[ch.x + 1]);
     uint32_t mnx = 0xffffffffu, mny = 0xffffffffu, mxx = 0u, mxy = 0u;
     for (int32_t i = ch.y + threadIdx.x; i < end; i += blockDim.x) {
-        const uint32_t ox = ord_from_float(pos[i]);
-        const uint32_t oy = ord_from_float(pos[n + i]);
+        float px, py;
+        if (pos4) {
+            const float2 q = *reinterpret_cast<const float2 *>(&pos4[i]);
+            px = q.x;
+            py = q.y;
+        } else {
+            px = pos[i];
+            py = pos[n + i];
+        }
+        const uint32_t ox = ord_from_float(px);
+        const uint32_t oy = ord_from_float(py);
         mnx = min(mnx, ox);
         mny = min(mny, oy);
         mxx = max(mxx, ox);
@@ -169,9 +181,10 @@ __global__ __launch_bounds__(kBboxBlock) void k_bbox(const float *__restrict__ p
     }
 }
 
-// Grid of every scene.  Cells are square, at least neighbor_dist * (1 + 2^-10)
+// Grid of every scene.  Cells are square, neighbor_dist * (1 + 2^-10) / 2
 // wide, so two agents closer than neighbor_dist (also after float32 rounding
-// of their squared distance) always sit in the same or adjacent cells.  If the
+// of their squared distance) always sit within two cells of each other in x
+// and in y (the neighbour search reads the disc's chords over them).  If the
 // total number of cells would exceed the budget, all cells are widened by a
 // common factor (more candidates per agent, same neighbours).  With spawning
 // and removal on (life), one more cell after all scenes' cells takes the
@@ -261,8 +274,11 @@ __device__ __forceinline__ void cell_of(const GridDev &g, float x, float y, int3
 // Cell key of every agent; an absent agent (not yet spawned at the step
 // counters->step, or removed) goes to the last cell, so it sorts after every
 // present agent and no cell of a scene holds it.  That cell can hold most of
-// the agents, so its ranks are taken with one atomic per wave.
+// the agents, so its ranks are taken with one atomic per wave.  pos4
+// (resident steps, never with spawning): positions in the previous step's
+// cell order; key and rank are then indexed by that order.
 __global__ __launch_bounds__(256) void k_key(const float *__restrict__ pos, int32_t n,
+                                             const float4 *__restrict__ pos4,
                                              const int32_t *__restrict__ agent_scene,
                                              const GridDev *__restrict__ grid,
                                              int32_t *__restrict__ key,
@@ -291,6 +307,35 @@ __global__ __launch_bounds__(256) void k_key(const float *__restrict__ pos, int3
                 rank[i] = base + before;
             }
         }
+    }
+    if (pos4) {
+        // resident step: agents come in the previous step's cell order, so
+        // neighbouring lanes mostly share a cell.  Each run of lanes with
+        // the same key takes its ranks with one atomic (the run's first lane
+        // adds the run's length and hands the base to the others).
+        int32_t k = -1;
+        if (valid) {
+            const GridDev g = grid[agent_scene[i]];
+            const float2 q = *reinterpret_cast<const float2 *>(&pos4[i]);
+            int32_t cx, cy;
+            cell_of(g, q.x, q.y, cx, cy);
+            k = g.base + cy * g.nx + cx;
+        }
+        const int lane = (int)(threadIdx.x & 63);
+        const int32_t kp = __shfl_up(k, 1, 64);
+        const uint64_t heads = __ballot(lane == 0 || kp != k);
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const int start = 63 - __clzll((long long)(heads & upto));
+        const uint64_t above = heads & ~upto;
+        const int next = above ? __ffsll((unsigned long long)above) - 1 : 64;
+        int32_t base = 0;
+        if (valid && lane == start) base = atomicAdd(&counts[k], next - start);
+        base = __shfl(base, start, 64);
+        if (valid) {
+            key[i] = k;
+            rank[i] = base + (lane - start);
+        }
+        return;
     }
     if (!valid || absent) return;
     const GridDev g = grid[agent_scene[i]];
@@ -393,8 +438,18 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(int32_t *__restrict__
     }
 }
 
+// Counting-sort scatter into cell order.  From the caller's arrays (agent
+// order), or in a resident step from the previous step's cell order (src4,
+// ids sid_prev, goals / preferred velocities sg_prev).  sg_cur (nullable)
+// receives the goals or preferred velocities in the new order: from sg_prev,
+// or from the caller's [2, N] array sg_src.
 __global__ __launch_bounds__(256) void k_scatter(const float *__restrict__ pos,
                                                  const float *__restrict__ vel, int32_t n,
+                                                 const float4 *__restrict__ src4,
+                                                 const int32_t *__restrict__ sid_prev,
+                                                 const float2 *__restrict__ sg_prev,
+                                                 const float *__restrict__ sg_src,
+                                                 float2 *__restrict__ sg_cur,
                                                  const int32_t *__restrict__ key,
                                                  const int32_t *__restrict__ rank,
                                                  const int32_t *__restrict__ cell_start,
@@ -408,15 +463,23 @@ __global__ __launch_bounds__(256) void k_scatter(const float *__restrict__ pos,
     if (i >= n) return;
     const int32_t k = key[i];
     const int32_t d = cell_start[k] + rank[i];
-    if (radius) srad[d] = radius[i];
     float4 r;
-    r.x = pos[i];
-    r.y = pos[n + i];
-    r.z = vel ? vel[i] : 0.f;
-    r.w = vel ? vel[n + i] : 0.f;
+    int32_t id = i;
+    if (src4) {
+        r = src4[i];
+        id = sid_prev[i];
+        if (sg_cur) sg_cur[d] = sg_prev[i];
+    } else {
+        r.x = pos[i];
+        r.y = pos[n + i];
+        r.z = vel ? vel[i] : 0.f;
+        r.w = vel ? vel[n + i] : 0.f;
+        if (sg_cur) sg_cur[d] = make_float2(sg_src[i], sg_src[n + i]);
+    }
+    if (radius) srad[d] = radius[id];
     sorted[d] = r;
-    sid[d] = i;
-    inv[i] = d;
+    sid[d] = id;
+    inv[id] = d;
 }
 
 // Velocities into the sorted copy for a velocity pass on an existing grid;
@@ -767,17 +830,23 @@ __device__ __forceinline__ void build_constraints(Rows &rows, const Src &src, in
     }
 }
 
+// sg (resident steps): the goal or preferred velocity by sorted index s.
 __device__ __forceinline__ void preferred_velocity(const SceneDev &p, const AgentProps &ag,
                                                    float4 me, int32_t id, int32_t n,
                                                    const float *__restrict__ pref,
-                                                   const float *__restrict__ goals, double &vhx,
-                                                   double &vhy)
+                                                   const float *__restrict__ goals,
+                                                   const float2 *__restrict__ sg, int32_t s,
+                                                   double &vhx, double &vhy)
 {
 #pragma clang fp contract(off)
+    float2 g = make_float2(0.f, 0.f);
+    if (sg) g = sg[s];
+    else if (goals) g = make_float2(goals[id], goals[n + id]);
+    else g = make_float2(pref[id], pref[n + id]);
     if (goals) {
         // walking speed toward the goal; the last step lands on it
-        const double ex = (double)goals[id] - (double)me.x;
-        const double ey = (double)goals[n + id] - (double)me.y;
+        const double ex = (double)g.x - (double)me.x;
+        const double ey = (double)g.y - (double)me.y;
         const double el = sqrt(ex * ex + ey * ey);
         const double s = (double)(ag.pref_speed ? ag.pref_speed[id] : p.pref_speed);
         const double dt = (double)p.dt;
@@ -789,8 +858,8 @@ __device__ __forceinline__ void preferred_velocity(const SceneDev &p, const Agen
             vhy = ey / dt;
         }
     } else {
-        vhx = (double)pref[id];
-        vhy = (double)pref[n + id];
+        vhx = (double)g.x;
+        vhy = (double)g.y;
     }
 }
 
@@ -800,10 +869,17 @@ constexpr int kModePlain = 0, kModeRec = 1, kModeLife = 2;
 
 template <bool LIFE>
 __device__ __forceinline__ void write_result(const OutArgs &o, float mex, float mey, float dtf,
-                                             int32_t id, int32_t n, double vx, double vy,
-                                             double vhx, double vhy, uint8_t status)
+                                             int32_t id, int32_t s, int32_t n, double vx,
+                                             double vy, double vhx, double vhy, uint8_t status)
 {
 #pragma clang fp contract(off)
+    if (o.nxt) {
+        // resident step: the new state stays in this step's cell order
+        const double dt = (double)dtf;
+        o.nxt[s] = make_float4((float)((double)mex + dt * vx), (float)((double)mey + dt * vy),
+                               (float)vx, (float)vy);
+        return;
+    }
     if (o.new_vel) {
         o.new_vel[id] = (float)vx;
         o.new_vel[n + id] = (float)vy;
@@ -849,7 +925,7 @@ __device__ __forceinline__ bool lp_agent(LpRows<KMAX> &rows, FallbackItem &it, c
 {
     constexpr bool REC = MODE == kModeRec, LIFE = MODE == kModeLife;
     double vhx, vhy;
-    preferred_velocity(p, out.ag, me, id, n, out.pref, out.goals, vhx, vhy);
+    preferred_velocity(p, out.ag, me, id, n, out.pref, out.goals, out.sg, s, vhx, vhy);
     const float vmaxf = out.ag.max_speed ? out.ag.max_speed[id] : p.vmax;
     const double vmax = (double)vmaxf;
     double vx, vy;
@@ -859,7 +935,7 @@ __device__ __forceinline__ bool lp_agent(LpRows<KMAX> &rows, FallbackItem &it, c
     const int fail = rows.project(m, vmax, vhx, vhy, vx, vy, &act);
     if (REC) out.tape_state[s] = me;
     if (fail < 0) {
-        write_result<LIFE>(out, me.x, me.y, p.dt, id, n, vx, vy, vhx, vhy, 0);
+        write_result<LIFE>(out, me.x, me.y, p.dt, id, s, n, vx, vy, vhx, vhy, 0);
         if (REC) {
             TapeCode tc{};
             tc.status = 0;
@@ -1169,6 +1245,17 @@ struct FbRows<KMAX, false> {
 // run the one-lane program.  Each partial starts from the disc's interval,
 // which is part of every line's program.
 
+// Lanes of one wave hand values to each other through LDS: the wave's LDS
+// accesses complete in issue order, so it takes only that neither the
+// compiler moves an access across this point (a wavefront-scope fence, which
+// emits no instruction) nor the lanes part (the wave barrier).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 constexpr int kWuGroup = 4;  // lanes per published line
 constexpr int kWuFrom = 6;   // fewest earlier rows (i + 1) worth splitting
 constexpr int kWuLines = kLpBlock / kWuGroup;
@@ -1250,7 +1337,7 @@ __device__ __forceinline__ bool lp2_plane_wu(const RS &L, WuShared<KB> &W, bool 
                 W.line[rank][7] = bk;
             }
             // one wave per block: its LDS accesses complete in issue order
-            __builtin_amdgcn_wave_barrier();
+            wave_lds_sync();
             const int g = lane / kWuGroup, r = lane % kWuGroup;
             const int per = (i + 1 + kWuGroup - 1) / kWuGroup;  // rows per share
             Interval part;
@@ -1303,7 +1390,7 @@ __device__ __forceinline__ bool lp2_plane_wu(const RS &L, WuShared<KB> &W, bool 
                 W.rsrc[g][0] = part.lo_src;
                 W.rsrc[g][1] = part.hi_src;
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_lds_sync();
             if (run) {
                 iv.lo_n = W.res[rank][0];
                 iv.lo_d = W.res[rank][1];
@@ -1313,7 +1400,7 @@ __device__ __forceinline__ bool lp2_plane_wu(const RS &L, WuShared<KB> &W, bool 
                 iv.hi_src = W.rsrc[rank][1];
             }
             // the next step's writes must not pass this step's reads
-            __builtin_amdgcn_wave_barrier();
+            wave_lds_sync();
         } else if (run) {
             iv.init(root, mm);
             for (int j = -1; j < i; ++j) {
@@ -1431,10 +1518,10 @@ __device__ __forceinline__ void fallback_items(RS &rows, WuShared<KMAX> *W, cons
                 W->ny[k][lane] = nk.y;
                 W->b[k][lane] = rows.B(k);
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_lds_sync();
             d = fallback_velocity<KMAX>(rows, m, fail, (double)it.vmax, it.vhx, it.vhy, vx, vy,
                                         &plane, &dact, &ract, &ok, Lp3WorkUnits<KMAX>{W});
-            __builtin_amdgcn_wave_barrier();
+            wave_lds_sync();
         } else {
             d = fallback_velocity<KMAX>(rows, m, fail, (double)it.vmax, it.vhx, it.vhy, vx, vy,
                                         &plane, &dact, &ract, &ok);
@@ -1452,8 +1539,8 @@ __device__ __forceinline__ void fallback_items(RS &rows, WuShared<KMAX> *W, cons
             tc.dstar = d;
             out.tape_codes[it.s] = tc;
         }
-        write_result<MODE == kModeLife>(out, it.mex, it.mey, it.dt, it.id, n, vx, vy, it.vhx,
-                                        it.vhy, 1);
+        write_result<MODE == kModeLife>(out, it.mex, it.mey, it.dt, it.id, it.s, n, vx, vy,
+                                        it.vhx, it.vhy, 1);
     }
 }
 
@@ -1630,12 +1717,12 @@ hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, bool 
     const int32_t n = pl.n;
     const LifeArgs &life = pl.out.life;
     if (n > 0)
-        hipLaunchKernelGGL(k_bbox, dim3(pl.n_chunks), dim3(kBboxBlock), 0, st, pos, n, pl.chunks,
-                           pl.off, pl.bbox);
+        hipLaunchKernelGGL(k_bbox, dim3(pl.n_chunks), dim3(kBboxBlock), 0, st, pos, n, pl.res_src,
+                           pl.chunks, pl.off, pl.bbox);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, pl.n_scenes, pl.off, pl.sp, pl.bbox,
                        pl.grid, pl.counters, pl.max_cells, life.spawn_step ? 1 : 0);
     if (n > 0)
-        hipLaunchKernelGGL(k_key, dim3((n + 255) / 256), dim3(256), 0, st, pos, n,
+        hipLaunchKernelGGL(k_key, dim3((n + 255) / 256), dim3(256), 0, st, pos, n, pl.res_src,
                            pl.agent_scene, pl.grid, pl.key, pl.rank, pl.counts, life.spawn_step,
                            life.state, pl.counters);
     // the scan covers the scenes' cells and the cell of absent agents
@@ -1646,9 +1733,9 @@ hipError_t launch_grid(const Plan &pl, const float *pos, const float *vel, bool 
                        pl.counters, pl.partial, pl.cell_start, n,
                        advance && life.spawn_step ? 1 : 0);
     if (n == 0) return hipGetLastError();
-    hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, st, pos, vel, n, pl.key,
-                       pl.rank, pl.cell_start, pl.sorted, pl.sid, pl.inv,
-                       pl.out.ag.radius, pl.out.ag.srad);
+    hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, st, pos, vel, n,
+                       pl.res_src, pl.sid_prev, pl.sg_prev, pl.sg_src, pl.sg_cur, pl.key, pl.rank,
+                       pl.cell_start, pl.sorted, pl.sid, pl.inv, pl.out.ag.radius, pl.out.ag.srad);
     return hipGetLastError();
 }
 

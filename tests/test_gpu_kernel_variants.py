@@ -233,3 +233,44 @@ def test_fallback_work_units_full_size_step():
         say("%d agents, %d fallback, %d differ (max %.3g m/s)"
             % (w.n, int((a["status"] == 1).sum()), ndiff, dv.max()))
         assert dv.max() <= 2.4e-7 and ndiff <= w.n // 1000
+
+
+RESIDENT_CASES = [
+    ("uniform_rsa goals", lambda: scenes.uniform_rsa(), True),
+    ("3000 no goals K=16", lambda: scenes.tiny_random(3000, 30.0, seed=213, max_neighbors=16),
+     False),
+    ("dense 20000", lambda: scenes.dense_uniform(n=20000, seed=214), True),
+    ("40 scenes", lambda: scenes.batched().subset_scenes(list(range(40))), True),
+    ("hetero crossing", lambda: scenes.crossing_hetero(n=2500), True),
+    ("ring 4096", lambda: scenes.ring(n=4096, radius_m=75.0), True),
+]
+
+
+@pytest.mark.parametrize("name,make,goals", RESIDENT_CASES, ids=[c[0] for c in RESIDENT_CASES])
+def test_resident_steps_equal_single_steps(name, make, goals):
+    """The inner steps of one multi-step call keep the state in cell order (only
+    the first reads and the last writes the caller's arrays): seven steps in
+    one call equal seven one-step calls bit for bit, with the split and the
+    fused velocity kernels, with goals or fixed preferred velocities, with
+    several scenes and with per-agent properties."""
+    torch = _torch()
+    from paper_1908_10107_amd import orca
+    w = make()
+    if not goals:
+        w.goals = None
+    say("case resident steps: %s, %d agents, %d scenes" % (name, w.n, w.n_scenes))
+    kmax = max(1, max(p.max_neighbors for p in w.params))
+    out = []
+    for apl, calls in ((0, [7]), (0, [1] * 7), (2, [7]), (0, [3, 1, 3])):
+        d = orca.to_device(w)
+        with orca.Context(max_agents=w.n, max_scenes=w.n_scenes, k_max=kmax) as ctx:
+            ctx.set_agents(d["radius"], d["max_speed"], d["pref_speed"])
+            ctx.set_kernels(apl, 12)
+            for c in calls:
+                ctx.step(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"],
+                         goals=d["goals"], n_steps=c)
+            torch.cuda.synchronize()
+        out.append({k: d[k].cpu().numpy() for k in ("pos", "vel", "pref_vel")})
+    for r in out[1:]:
+        for k in out[0]:
+            assert np.array_equal(out[0][k], r[k]), k
