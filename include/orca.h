@@ -299,6 +299,37 @@ int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
 int orca_profile(orca_ctx *ctx, int32_t enable);
 int orca_profile_read(orca_ctx *ctx, double *stage_ms, int64_t *passes, int64_t *fallback_agents);
 
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * orca_step for ONE scene of n_agents agents without a context: the same
+ * kernels and results as orca_step on a fresh context (default launch
+ * shapes, no tape, no per-agent properties, no spawning), with every scratch
+ * buffer in a file-scope device array of ORCA_NOALLOC_SCRATCH_BYTES (about
+ * 9.2 MiB) that each device the library runs on holds until the process
+ * ends.  It calls no hipMalloc, hipFree or allocating library routine and
+ * enqueues kernels only (no memset or copy nodes), so it can be captured.
+ *   n_agents: 0 .. ORCA_NOALLOC_MAX_AGENTS; params: host, one scene with
+ *   max_neighbors 0 .. ORCA_NOALLOC_MAX_NEIGHBORS; pos, vel, pref_vel,
+ *   goals (nullable): caller-owned device [2, N] as for orca_step (goals
+ *   given: pref_vel is overwritten with the steered preferred velocity);
+ *   n_steps >= 1; hip_stream: a hipStream_t of the CURRENT device (NULL =
+ *   null stream); err: nullable host buffer of err_len bytes for a message.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (each call clears what must start at zero): calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller.
+ * Errors: ECAPACITY (n_agents or max_neighbors above the maximum), EINVAL,
+ * EHIP.  Nothing is enqueued when the arguments are rejected.
+ */
+#define ORCA_NOALLOC_MAX_AGENTS 16384
+#define ORCA_NOALLOC_MAX_NEIGHBORS 16
+#define ORCA_NOALLOC_SCRATCH_BYTES 9685760
+int orca_step_noalloc(int64_t n_agents, const orca_params *params, float *pos, float *vel,
+                      float *pref_vel, const float *goals, int32_t n_steps, void *hip_stream,
+                      char *err, int32_t err_len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liborca.so")
-SOURCES = ["orca_kernels.hip", "orca_adjoint.hip", "orca_api.hip"]
+SOURCES = ["orca_kernels.hip", "orca_adjoint.hip", "orca_api.hip", "orca_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

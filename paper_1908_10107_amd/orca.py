@@ -94,6 +94,9 @@ def load(path: str = LIB_PATH):
     L.orca_profile.restype = ctypes.c_int
     L.orca_profile_read.argtypes = [_P, _P, _P, _P]
     L.orca_profile_read.restype = ctypes.c_int
+    L.orca_step_noalloc.argtypes = [ctypes.c_int64, _P, _P, _P, _P, _P, ctypes.c_int32, _P, _P,
+                                    ctypes.c_int32]
+    L.orca_step_noalloc.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -323,6 +326,28 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+
+NOALLOC_MAX_AGENTS = 16384
+NOALLOC_MAX_NEIGHBORS = 16
+
+
+def step_noalloc(params, pos, vel, pref_vel, goals=None, n_steps=1):
+    """orca_step_noalloc: n_steps of one scene (params: one scenes.SceneParams)
+    on torch's current stream, with the library's static scratch array instead
+    of a context (see include/orca.h for its limits)."""
+    import torch
+    lib = load()
+    n = pos.shape[1]
+    pa = params_array([params])
+    err = ctypes.create_string_buffer(512)
+    stream = torch.cuda.current_stream(pos.device).cuda_stream
+    with torch.cuda.device(pos.device):
+        rc = lib.orca_step_noalloc(int(n), pa, _dev_ptr(pos, "pos", n), _dev_ptr(vel, "vel", n),
+                                   _dev_ptr(pref_vel, "pref_vel", n), _dev_ptr(goals, "goals", n),
+                                   int(n_steps), ctypes.c_void_p(stream), err, len(err))
+    if rc != OK:
+        raise OrcaError(rc, err.value.decode())
 
 
 def to_device(w, device="cuda"):
