@@ -420,7 +420,6 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="dense_uniform")
-    ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="the CPU reference steps the workload until this much time has passed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -467,6 +466,9 @@ def main():
         step(args.warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # per-stage HIP events recorded on the library's stream inside the timed
+    # steps themselves (no waiting; read after the timed region)
+    ctx.profile(2)
     t0 = time.perf_counter()
     e0.record()
     step(args.steps)
@@ -476,15 +478,11 @@ def main():
     gpu_ms = e0.elapsed_time(e1)
     ms_per_step = 1e3 * wall / args.steps
     value = w.n * args.steps / wall
+    ms, passes, fb = ctx.profile_read()
+    ctx.profile(False)
     print("# timed %d steps: %.3f s wall, %.3f s on the stream" % (args.steps, wall,
                                                                   gpu_ms / 1e3),
           file=sys.stderr, flush=True)
-
-    # per-stage timing on a separate pass (each step waits for its stream)
-    ctx.profile(True)
-    step(args.profile_steps)
-    ms, passes, fb = ctx.profile_read()
-    ctx.profile(False)
     avg = [m / max(passes, 1) for m in ms]
     fb_avg = fb / max(passes, 1)
     dom = int(np.argmax(avg))
@@ -499,8 +497,11 @@ def main():
         others[orca.STAGE_NAMES[i]] = {"bound": b_, "achieved": round(a_, 4), "unit": u_,
                                        "frac": round(a_ / p_, 6)}
     kdisp = 10 if kmax <= 10 else (16 if kmax <= 16 else 32)
-    kname = ("k_key", "k_knn<%d>" % kdisp, "k_lp<%d,0>" % kdisp,
-             "k_fallback<%d,0>" % kdisp)[dom]
+    apl = tuned[2] if tuned is not None and len(tuned) > 2 else 0
+    wu = tuned[4] if tuned is not None and len(tuned) > 4 else 0
+    kname = ("k_key", "k_knn<%d>" % kdisp,
+             "k_velocity<%d,%d>" % (kdisp, apl) if apl else "k_lp<%d,0>" % kdisp,
+             "k_fallback<%d,0,%s>" % (kdisp, "true" if wu else "false"))[dom]
     traffic = profiled_traffic(kname) if args.workload == "dense_uniform" else None
     # the whole step against HBM: 144 B per agent + 12 B per cell, each array
     # touched once (state, sort, neighbour state, outputs, goals)

@@ -160,10 +160,14 @@ int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
  * orca_step for many steps at the lowest launch cost: the first call captures
  * one whole step (every kernel of every scene; no host synchronisation and no
  * memory set nodes inside) into a HIP graph on a private capture stream, and
- * every step replays that graph on the context stream.  The graph is captured
- * again when pos / vel / pref_vel / goals, the scene set or the launch shapes
- * change.  The first call waits for the context stream once.  Not available
- * while profiling is on (ESTATE).  No tape is recorded.
+ * every step replays that graph on the context stream.  For 10 or more steps
+ * without spawning and removal it also captures a block of 10 steps that, as
+ * orca_step does, keeps the state in cell order between its steps; n_steps
+ * then replays n_steps / 10 blocks and the rest one step at a time (the same
+ * results bit for bit).  The graphs are captured again when pos / vel /
+ * pref_vel / goals, the scene set or the launch shapes change.  A capture
+ * waits for the context stream once.  Not available while profiling is on
+ * (ESTATE).  No tape is recorded.
  */
 int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
                     const orca_params *params, float *pos, float *vel, float *pref_vel,
@@ -286,14 +290,17 @@ int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
 /*
  * Diagnostics: per-stage GPU time of every pass (orca_compute_velocities, or
  * one step of orca_step) measured with HIP events recorded on the context
- * stream between the stages.  While enabled, each pass waits for its stream
- * at the end (so enable it only for measurement).  Stages:
+ * stream between the stages.  Stages:
  *   0 binning (bounding box, keys, scan, scatter; 0 for orca_compute_velocities),
  *   1 neighbour gather, 2 half-planes + 2D LP, 3 least-penetration fallback.
- * orca_profile(ctx, 1) clears the sums and starts; orca_profile(ctx, 0) stops.
- * orca_profile_read gives the summed milliseconds per stage (stage_ms
- * [ORCA_PROF_STAGES]), the number of passes, and the total number of agents
- * that took the fallback in them.
+ * orca_profile(ctx, 1) clears the sums and starts with each pass waiting for
+ * its stream at the end (so the sums are always current); orca_profile(ctx,
+ * 2) clears them and starts without waiting: the events of the first 1024
+ * passes are recorded and the fallback agents counted on the device, and
+ * orca_profile_read waits for the stream and sums them (use it around timed
+ * work).  orca_profile(ctx, 0) stops.  orca_profile_read gives the summed
+ * milliseconds per stage (stage_ms [ORCA_PROF_STAGES]), the number of passes,
+ * and the total number of agents that took the fallback in them.
  */
 #define ORCA_PROF_STAGES 4
 int orca_profile(orca_ctx *ctx, int32_t enable);

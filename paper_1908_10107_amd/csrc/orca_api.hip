@@ -83,6 +83,11 @@ struct orca_ctx {
 
     // per-stage timing (diagnostics): events on the context stream between stages
     bool profiling = false;
+    // mode 2: events of every pass recorded without waiting (read at the end);
+    // the fallback agents of those passes are summed on the device
+    int32_t prof_mode = 0;
+    std::vector<hipEvent_t> pev;
+    unsigned long long *fb_total = nullptr;
     hipEvent_t ev[ORCA_PROF_STAGES + 1] = {};
     double stage_ms[ORCA_PROF_STAGES] = {0};
     int64_t prof_steps = 0, prof_fallback = 0;
@@ -107,10 +112,13 @@ struct orca_ctx {
     int32_t vel_apl = 0, vel_waves_per_cu = 12;  // velocity kernels (orca_set_kernels)
     int32_t fb_work_units = 0;                   // fallback with work units (orca_set_kernels)
 
-    // step graph: one captured step replayed by orca_step_graph
+    // step graphs replayed by orca_step_graph: one step, and a block of
+    // kGraphBlock resident steps (plain steps only)
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t gblock = nullptr;
+    hipGraphExec_t gblock_exec = nullptr;
     const void *graph_key[9] = {};
     uint64_t graph_scene_version = 0, scene_version = 0;
     int32_t graph_knn_block = 0, graph_fb = 0, graph_apl = -1, graph_vw = 0, graph_wu = -1;
@@ -283,16 +291,25 @@ orca::Plan make_plan(const orca_ctx *ctx)
     return p;
 }
 
-#define STAGE_MARK(i)                                                        \
-    do {                                                                     \
-        if (ctx->profiling) HIP_OK(hipEventRecord(ctx->ev[(i)], ctx->stream)); \
+constexpr int64_t kProfPasses = 1024;  // passes a no-wait profile records
+
+#define STAGE_MARK(i)                                                                     \
+    do {                                                                                  \
+        if (ctx->profiling && ctx->prof_mode == 1)                                        \
+            HIP_OK(hipEventRecord(ctx->ev[(i)], ctx->stream));                            \
+        if (ctx->profiling && ctx->prof_mode == 2 && ctx->prof_steps < kProfPasses)       \
+            HIP_OK(hipEventRecord(ctx->pev[ctx->prof_steps * (ORCA_PROF_STAGES + 1) + (i)], \
+                                  ctx->stream));                                          \
     } while (0)
 
 // Enqueue one pass: optional grid build, then neighbours, 2D LP, fallback.
 // With profiling on, the stream is drained after the pass and the time
 // between the stage events is accumulated.
-int run_pass(orca_ctx *ctx, const orca::Plan &pl, const float *grid_pos, const float *grid_vel)
+int run_pass(orca_ctx *ctx, const orca::Plan &pl_in, const float *grid_pos, const float *grid_vel)
 {
+    orca::Plan pl = pl_in;
+    if (ctx->profiling && ctx->prof_mode == 2 && ctx->prof_steps < kProfPasses)
+        pl.fb_total = ctx->fb_total;
     STAGE_MARK(0);
     if (grid_pos) {
         HIP_OK(orca::launch_grid(pl, grid_pos, grid_vel, true, ctx->stream));
@@ -305,6 +322,10 @@ int run_pass(orca_ctx *ctx, const orca::Plan &pl, const float *grid_pos, const f
     STAGE_MARK(3);
     HIP_OK(orca::launch_fallback(pl, ctx->kmax_cur, ctx->stream));
     STAGE_MARK(4);
+    if (ctx->profiling && ctx->prof_mode == 2) {
+        if (ctx->prof_steps < kProfPasses) ctx->prof_steps += 1;
+        return ORCA_OK;
+    }
     if (ctx->profiling) {
         HIP_OK(hipEventSynchronize(ctx->ev[ORCA_PROF_STAGES]));
         for (int i = 0; i < ORCA_PROF_STAGES; ++i) {
@@ -320,13 +341,39 @@ int run_pass(orca_ctx *ctx, const orca::Plan &pl, const float *grid_pos, const f
     return ORCA_OK;
 }
 
+// Buffers of step t of a resident run of n plain steps: the state stays in
+// cell order between steps, so only the first step reads and only the last
+// writes the caller's arrays in agent order.  Results equal those of one-step
+// calls bit for bit (nothing depends on the order within a cell).  The id and
+// goal buffers alternate so that the last step's ids are in ctx->sid.
+void resident_step(const orca_ctx *ctx, orca::Plan &pl, int32_t t, int32_t n, const float *src)
+{
+    const int cur = (n - 1 - t) & 1;
+    const bool in = t > 0, out = t < n - 1;
+    pl.sid = cur == 0 ? ctx->sid : ctx->sid2;
+    pl.sid_prev = in ? (cur == 0 ? ctx->sid2 : ctx->sid) : nullptr;
+    pl.res_src = in ? ctx->nxt : nullptr;
+    pl.sg_cur = ctx->sg[cur];
+    pl.sg_prev = in ? ctx->sg[cur ^ 1] : nullptr;
+    pl.sg_src = in ? nullptr : src;
+    pl.out.sg = ctx->sg[cur];
+    pl.out.nxt = out ? ctx->nxt : nullptr;
+}
+
 void drop_graph(orca_ctx *c)
 {
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->gblock_exec) (void)hipGraphExecDestroy(c->gblock_exec);
+    if (c->gblock) (void)hipGraphDestroy(c->gblock);
     c->graph_exec = nullptr;
     c->graph = nullptr;
+    c->gblock_exec = nullptr;
+    c->gblock = nullptr;
 }
+
+// Resident steps a block graph of orca_step_graph holds.
+constexpr int32_t kGraphBlock = 10;
 
 void free_all(orca_ctx *c)
 {
@@ -340,6 +387,9 @@ void free_all(orca_ctx *c)
             (void)hipEventDestroy(c->ev[i]);
             c->ev[i] = nullptr;
         }
+    for (hipEvent_t &e : c->pev)
+        if (e) (void)hipEventDestroy(e);
+    c->pev.clear();
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
 }
@@ -420,6 +470,7 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->sid2, sizeof(int32_t) * A) &&
               alloc((void **)&ctx->sg[0], sizeof(float2) * A) &&
               alloc((void **)&ctx->sg[1], sizeof(float2) * A) &&
+              alloc((void **)&ctx->fb_total, sizeof(unsigned long long)) &&
               alloc((void **)&ctx->acc, sizeof(double) * 4 * A) &&
               alloc((void **)&ctx->acc_scene, sizeof(double) * 2 * S);
     const size_t T = (size_t)tape_steps;
@@ -585,25 +636,10 @@ int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
     pl.out.goals = goals;
     ctx->grid_valid = false;
     if (save_tape) ctx->tape_len = 0;
-    // Plain steps of a multi-step call keep the state in cell order between
-    // steps (resident): only the first step reads and only the last writes
-    // the caller's arrays in agent order.  Results are the same bit for bit
-    // (nothing depends on the order within a cell).  The buffers alternate so
-    // that the last step's ids are in ctx->sid.
+    // plain steps of a multi-step call run resident (resident_step)
     const bool resident = n_steps > 1 && !save_tape && !ctx->l_spawn;
     for (int32_t t = 0; t < n_steps; ++t) {
-        if (resident) {
-            const int cur = (n_steps - 1 - t) & 1;
-            const bool in = t > 0, out = t < n_steps - 1;
-            pl.sid = cur == 0 ? ctx->sid : ctx->sid2;
-            pl.sid_prev = in ? (cur == 0 ? ctx->sid2 : ctx->sid) : nullptr;
-            pl.res_src = in ? ctx->nxt : nullptr;
-            pl.sg_cur = ctx->sg[cur];
-            pl.sg_prev = in ? ctx->sg[cur ^ 1] : nullptr;
-            pl.sg_src = in ? nullptr : (goals ? goals : pref_vel);
-            pl.out.sg = ctx->sg[cur];
-            pl.out.nxt = out ? ctx->nxt : nullptr;
-        }
+        if (resident) resident_step(ctx, pl, t, n_steps, goals ? goals : pref_vel);
         if (save_tape) {
             // the step's neighbour lists and cell-order ids go straight to
             // the tape slot; state and choices are written by sorted index
@@ -648,8 +684,13 @@ int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
                        ctx->graph_fb == ctx->fb_waves_per_cu && ctx->graph_apl == ctx->vel_apl &&
                        ctx->graph_vw == ctx->vel_waves_per_cu &&
                        ctx->graph_wu == ctx->fb_work_units;
+    // blocks of resident steps for plain steps (not with spawning and removal)
+    const bool blocks = !ctx->l_spawn && n_steps >= kGraphBlock;
     if (!fresh) {
         drop_graph(ctx);
+        memset(ctx->graph_key, 0, sizeof(ctx->graph_key));
+    }
+    if (!ctx->graph_exec || (blocks && !ctx->gblock_exec)) {
         if (!ctx->cap_stream) HIP_OK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         // the uploads of use_scenes must be done before the captured kernels replay
         HIP_OK(hipStreamSynchronize(ctx->stream));
@@ -658,24 +699,39 @@ int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
         pl.out.vel = vel;
         pl.out.pref = pref_vel;
         pl.out.goals = goals;
-        hipStream_t user = ctx->stream;
-        ctx->stream = ctx->cap_stream;
-        hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            rc = run_pass(ctx, pl, pos, vel);
-            hipGraph_t g = nullptr;
-            hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
-            ctx->graph = g;
-            if (rc == ORCA_OK && e2 != hipSuccess) rc = hip_fail(ctx, e2, "hipStreamEndCapture");
-        } else {
-            rc = hip_fail(ctx, e, "hipStreamBeginCapture");
-        }
-        ctx->stream = user;
+        // capture one step (nb == 1) or a block of nb resident steps
+        auto capture = [&](int32_t nb, hipGraph_t *graph, hipGraphExec_t *exec) -> int {
+            hipStream_t user = ctx->stream;
+            ctx->stream = ctx->cap_stream;
+            int r = ORCA_OK;
+            hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                orca::Plan q = pl;
+                for (int32_t t = 0; t < nb && r == ORCA_OK; ++t) {
+                    if (nb > 1) resident_step(ctx, q, t, nb, goals ? goals : pref_vel);
+                    r = run_pass(ctx, q, pos, vel);
+                }
+                hipGraph_t g = nullptr;
+                hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
+                *graph = g;
+                if (r == ORCA_OK && e2 != hipSuccess) r = hip_fail(ctx, e2, "hipStreamEndCapture");
+            } else {
+                r = hip_fail(ctx, e, "hipStreamBeginCapture");
+            }
+            ctx->stream = user;
+            if (r == ORCA_OK) {
+                e = hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) r = hip_fail(ctx, e, "hipGraphInstantiate");
+            }
+            return r;
+        };
+        if (!ctx->graph_exec) rc = capture(1, &ctx->graph, &ctx->graph_exec);
+        if (rc == ORCA_OK && blocks && !ctx->gblock_exec)
+            rc = capture(kGraphBlock, &ctx->gblock, &ctx->gblock_exec);
         if (rc != ORCA_OK) {
             drop_graph(ctx);
             return rc;
         }
-        HIP_OK(hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0));
         memcpy(ctx->graph_key, key, sizeof(key));
         ctx->graph_scene_version = ctx->scene_version;
         ctx->graph_knn_block = ctx->knn_block;
@@ -684,7 +740,11 @@ int orca_step_graph(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offset
         ctx->graph_vw = ctx->vel_waves_per_cu;
         ctx->graph_wu = ctx->fb_work_units;
     }
-    for (int32_t t = 0; t < n_steps; ++t) HIP_OK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    int32_t t = 0;
+    if (blocks)
+        for (; t + kGraphBlock <= n_steps; t += kGraphBlock)
+            HIP_OK(hipGraphLaunch(ctx->gblock_exec, ctx->stream));
+    for (; t < n_steps; ++t) HIP_OK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
     return ORCA_OK;
 }
 
@@ -813,11 +873,20 @@ int orca_set_kernels(orca_ctx *ctx, int32_t agents_per_lane, int32_t velocity_wa
 int orca_profile(orca_ctx *ctx, int32_t enable)
 {
     if (!ctx) return ORCA_EINVAL;
-    if (enable) {
+    if (enable < 0 || enable > 2) return fail(ctx, ORCA_EINVAL, "enable must be 0, 1 or 2");
+    if (enable == 1) {
         for (int i = 0; i <= ORCA_PROF_STAGES; ++i)
             if (!ctx->ev[i]) HIP_OK(hipEventCreate(&ctx->ev[i]));
     }
+    if (enable == 2) {
+        if (ctx->pev.empty()) {
+            ctx->pev.assign((size_t)kProfPasses * (ORCA_PROF_STAGES + 1), nullptr);
+            for (hipEvent_t &e : ctx->pev) HIP_OK(hipEventCreate(&e));
+        }
+        HIP_OK(hipMemsetAsync(ctx->fb_total, 0, sizeof(unsigned long long), ctx->stream));
+    }
     ctx->profiling = enable != 0;
+    ctx->prof_mode = enable;
     for (int i = 0; i < ORCA_PROF_STAGES; ++i) ctx->stage_ms[i] = 0.0;
     ctx->prof_steps = 0;
     ctx->prof_fallback = 0;
@@ -827,6 +896,21 @@ int orca_profile(orca_ctx *ctx, int32_t enable)
 int orca_profile_read(orca_ctx *ctx, double *stage_ms, int64_t *passes, int64_t *fallback_agents)
 {
     if (!ctx || !stage_ms) return ORCA_EINVAL;
+    if (ctx->profiling && ctx->prof_mode == 2) {
+        // the recorded passes' events, summed once the stream has reached them
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < ORCA_PROF_STAGES; ++i) ctx->stage_ms[i] = 0.0;
+        for (int64_t p = 0; p < ctx->prof_steps; ++p)
+            for (int i = 0; i < ORCA_PROF_STAGES; ++i) {
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, ctx->pev[p * (ORCA_PROF_STAGES + 1) + i],
+                                           ctx->pev[p * (ORCA_PROF_STAGES + 1) + i + 1]));
+                ctx->stage_ms[i] += ms;
+            }
+        unsigned long long fb = 0;
+        HIP_OK(hipMemcpy(&fb, ctx->fb_total, sizeof(fb), hipMemcpyDeviceToHost));
+        ctx->prof_fallback = (int64_t)fb;
+    }
     for (int i = 0; i < ORCA_PROF_STAGES; ++i) stage_ms[i] = ctx->stage_ms[i];
     if (passes) *passes = ctx->prof_steps;
     if (fallback_agents) *fallback_agents = ctx->prof_fallback;

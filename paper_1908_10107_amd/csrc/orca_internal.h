@@ -128,6 +128,7 @@ struct Plan {
     const float2 *sg_prev;
     const float *sg_src;
     float2 *sg_cur;
+    unsigned long long *fb_total;  // profiling: the pass's fallback count is added here
     OutArgs out;
 };
 

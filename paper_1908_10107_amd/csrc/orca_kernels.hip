@@ -558,18 +558,90 @@ __device__ __forceinline__ void knn_run(uint64_t (&best)[KMAX], uint32_t &lim, u
     }
 }
 
+// Offer every candidate within reach of an agent (me, id myid, its cell's grid
+// g, float32 neighbor_dist ndf) to its sorted key list, each row of cells over
+// the run its chord of the disc touches (one contiguous run of sorted
+// indices).  Cells are about nd/2 wide, so the disc of radius nd reaches two
+// rows and columns out (one once the grid was widened to nd).  The chords are
+// taken a little wider than the radius, so rounding of the cell arithmetic
+// or of the float32 distance never drops a neighbour: the distance test
+// decides.
+//
+// Order: first the 3 x 3 cells around the agent's own (about nd wide, so
+// they hold the K nearest in all but sparse crowds), then the rest, with each
+// chord cut to the list's current limit (the K-th distance once the list is
+// full): the list fills with near candidates first and the outer cells offer
+// few, which a wave would otherwise pay for with an insertion whenever any of
+// its lanes inserts.  The set that can enter is the same, so the result is.
+#ifndef ORCA_KNN_ORDER
+#define ORCA_KNN_ORDER 1
+#endif
+template <int KMAX>
+__device__ __forceinline__ void knn_rows(uint64_t (&best)[KMAX], uint32_t &lim, uint32_t nd_lim,
+                                         float4 me, uint32_t myid, const GridDev &g, float ndf,
+                                         const float4 *__restrict__ sorted,
+                                         const int32_t *__restrict__ sid,
+                                         const int32_t *__restrict__ cell_start)
+{
+    int32_t cx, cy;  // the agent's cell
+    cell_of(g, me.x, me.y, cx, cy);
+    const double cell = g.cell, nd = (double)ndf;
+    // rows and columns the disc of radius nd can reach: nd / cell rounded up
+    // (cells are a little wider than nd / kCellsPerNd, or wider still once the
+    // grid was widened)
+    const int32_t reach = max(1, min(kCellsPerNd, (int32_t)ceil(nd / cell)));
+    const double px = (double)me.x, py = (double)me.y;
+    const double slack = 1e-9 * (1.0 + fabs(px) + fabs(py));
+    // segments (one knn_run call site keeps the registers of one row loop):
+    // ORCA_KNN_ORDER 1: 0-2 the inner three columns of rows 0, -1, +1 over
+    // the full chord; 3-8 the columns left and right of them in the same rows
+    // and 9-10 rows -2, +2, over chords cut to the list's current limit.
+    // ORCA_KNN_ORDER 0: rows 0, -1, +1, -2, +2 over their full chords.
+    constexpr int32_t kSegs = ORCA_KNN_ORDER ? 11 : 5;
+#pragma unroll 1
+    for (int32_t q = 0; q < kSegs; ++q) {
+        int32_t qr = q, part = 0;  // row code, and 0 whole / 1 inner / 2 left / 3 right
+        if (ORCA_KNN_ORDER) {
+            qr = q < 3 ? q : (q < 9 ? (q - 3) >> 1 : q - 6);
+            part = q < 3 ? 1 : (q < 9 ? 2 + ((q - 3) & 1) : 0);
+        }
+        const int32_t dy = (qr & 1) ? -((qr + 1) >> 1) : (qr >> 1);  // 0, -1, +1, -2, +2
+        if (dy > reach || -dy > reach) continue;
+        const int32_t row = cy + dy;
+        if (row < 0 || row >= g.ny) continue;
+        // the chord's radius: nd, or the list's current limit after the inner cells
+        const double r = (ORCA_KNN_ORDER && part != 1)
+                             ? fmin(nd, sqrt((double)__uint_as_float(lim))) : nd;
+        const double rx = r * (1.0 + 1e-6) + slack;
+        double dyc = 0.0;  // distance from the agent to the row's band in y
+        if (dy > 0) dyc = fmax(g.y0 + (double)row * cell - py, 0.0);
+        if (dy < 0) dyc = fmax(py - (g.y0 + (double)(row + 1) * cell), 0.0);
+        if (dyc >= rx) continue;
+        const double hw = sqrt(rx * rx - dyc * dyc);
+        int32_t c0 = max((int32_t)fmax(floor((px - hw - g.x0) / cell), -1.0), max(cx - reach, 0));
+        int32_t c1 = min((int32_t)fmin(floor((px + hw - g.x0) / cell), (double)g.nx),
+                         min(cx + reach, g.nx - 1));
+        if (part == 1) {
+            c0 = max(c0, cx - 1);
+            c1 = min(c1, cx + 1);
+        } else if (part == 2) {
+            c1 = min(c1, cx - 2);
+        } else if (part == 3) {
+            c0 = max(c0, cx + 2);
+        }
+        if (c0 > c1) continue;
+        const int32_t rb = g.base + row * g.nx;
+        knn_run<KMAX>(best, lim, nd_lim, me.x, me.y, myid, cell_start[rb + c0],
+                      cell_start[rb + c1 + 1], sorted, sid);
+    }
+}
+
 // The K nearest of one agent (me, id myid, in a scene with grid g, cap K and
 // float32 neighbor_dist^2 nd2) among the agents of the cells within
 // neighbor_dist, strictly inside it, nearest first, ties by agent id, as
 // packed keys in best (see knn_offer).  Returns the number of leading slots
 // that hold the key 0 (KMAX - K; KMAX when K == 0 or nd2 admits nobody).
-//
-// Each row within reach is read over the cells its chord of the disc touches
-// (one contiguous run of sorted indices), own row first.  Cells are about
-// nd/2 wide, so the disc of radius nd reaches two rows and columns out (one
-// once the grid was widened to nd).  The chord is taken a little wider than
-// nd, so rounding of the cell arithmetic or of the float32 distance never
-// drops a neighbour: the distance test decides.
+// The candidates come from knn_rows.
 template <int KMAX>
 __device__ __forceinline__ int32_t knn_search(uint64_t (&best)[KMAX], float4 me, int32_t myid,
                                               const GridDev &g, int32_t K, float nd2, float ndf,
@@ -589,32 +661,7 @@ __device__ __forceinline__ int32_t knn_search(uint64_t (&best)[KMAX], float4 me,
     for (int k = 0; k < KMAX; ++k) best[k] = k < pad ? 0ull : ~0ull;
     const uint32_t nd_lim = __float_as_uint(nd2) - 1u;
     uint32_t lim = nd_lim;
-    int32_t cx, cy;  // the agent's cell
-    cell_of(g, me.x, me.y, cx, cy);
-    const double cell = g.cell, nd = (double)ndf;
-    // rows and columns the disc of radius nd can reach: nd / cell rounded up
-    // (cells are a little wider than nd / kCellsPerNd, or wider still once the
-    // grid was widened)
-    const int32_t reach = max(1, min(kCellsPerNd, (int32_t)ceil(nd / cell)));
-    const double px = (double)me.x, py = (double)me.y;
-    const double ndx = nd * (1.0 + 1e-6) + 1e-9 * (1.0 + fabs(px) + fabs(py));
-    for (int32_t q = 0; q <= 2 * reach; ++q) {
-        const int32_t dy = (q & 1) ? -((q + 1) >> 1) : (q >> 1);  // 0, -1, +1, -2, +2
-        const int32_t row = cy + dy;
-        if (row < 0 || row >= g.ny) continue;
-        double dyc = 0.0;  // distance from the agent to the row's band in y
-        if (dy > 0) dyc = fmax(g.y0 + (double)row * cell - py, 0.0);
-        if (dy < 0) dyc = fmax(py - (g.y0 + (double)(row + 1) * cell), 0.0);
-        if (dyc >= ndx) continue;
-        const double hw = sqrt(ndx * ndx - dyc * dyc);
-        const int32_t c0 = max((int32_t)fmax(floor((px - hw - g.x0) / cell), -1.0), max(cx - reach, 0));
-        const int32_t c1 = min((int32_t)fmin(floor((px + hw - g.x0) / cell), (double)g.nx),
-                               min(cx + reach, g.nx - 1));
-        if (c0 > c1) continue;
-        const int32_t rb = g.base + row * g.nx;
-        knn_run<KMAX>(best, lim, nd_lim, me.x, me.y, (uint32_t)myid, cell_start[rb + c0],
-                      cell_start[rb + c1 + 1], sorted, sid);
-    }
+    knn_rows<KMAX>(best, lim, nd_lim, me, (uint32_t)myid, g, ndf, sorted, sid, cell_start);
     return pad;
 }
 
@@ -635,8 +682,12 @@ __device__ __forceinline__ int32_t knn_entry(const uint64_t (&best)[KMAX], int k
 // same search, written out: this kernel keeps the registers of six waves per
 // SIMD only in this form).  Writes nbr[k * ld + s] (entries as knn_entry
 // gives them) and ncount[s].
+#ifndef ORCA_KNN_WAVES
+#define ORCA_KNN_WAVES 6
+#endif
 template <int KMAX>
-__global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
+__global__ __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(KMAX <= 16 ? ORCA_KNN_WAVES : 1))) void k_knn(const float4 *__restrict__ sorted,
                                              const int32_t *__restrict__ sid,
                                              const int32_t *__restrict__ inv,
                                              const int32_t *__restrict__ cell_start,
@@ -667,36 +718,11 @@ __global__ __launch_bounds__(512) void k_knn(const float4 *__restrict__ sorted,
     }
     const uint32_t nd_lim = __float_as_uint(nd2) - 1u;
     uint32_t lim = nd_lim;
-    int32_t cx, cy;  // the agent's cell
-    cell_of(g, me.x, me.y, cx, cy);
     uint64_t best[KMAX];
     const int32_t pad = KMAX - K;  // leading slots that hold the key 0
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) best[k] = k < pad ? 0ull : ~0ull;
-    const double cell = g.cell, nd = (double)sp[sc].nd;
-    // rows and columns the disc of radius nd can reach: nd / cell rounded up
-    // (cells are a little wider than nd / kCellsPerNd, or wider still once the
-    // grid was widened)
-    const int32_t reach = max(1, min(kCellsPerNd, (int32_t)ceil(nd / cell)));
-    const double px = (double)me.x, py = (double)me.y;
-    const double ndx = nd * (1.0 + 1e-6) + 1e-9 * (1.0 + fabs(px) + fabs(py));
-    for (int32_t q = 0; q <= 2 * reach; ++q) {
-        const int32_t dy = (q & 1) ? -((q + 1) >> 1) : (q >> 1);  // 0, -1, +1, -2, +2
-        const int32_t row = cy + dy;
-        if (row < 0 || row >= g.ny) continue;
-        double dyc = 0.0;  // distance from the agent to the row's band in y
-        if (dy > 0) dyc = fmax(g.y0 + (double)row * cell - py, 0.0);
-        if (dy < 0) dyc = fmax(py - (g.y0 + (double)(row + 1) * cell), 0.0);
-        if (dyc >= ndx) continue;
-        const double hw = sqrt(ndx * ndx - dyc * dyc);
-        const int32_t c0 = max((int32_t)fmax(floor((px - hw - g.x0) / cell), -1.0), max(cx - reach, 0));
-        const int32_t c1 = min((int32_t)fmin(floor((px + hw - g.x0) / cell), (double)g.nx),
-                               min(cx + reach, g.nx - 1));
-        if (c0 > c1) continue;
-        const int32_t rb = g.base + row * g.nx;
-        knn_run<KMAX>(best, lim, nd_lim, me.x, me.y, (uint32_t)myid, cell_start[rb + c0],
-                      cell_start[rb + c1 + 1], sorted, sid);
-    }
+    knn_rows<KMAX>(best, lim, nd_lim, me, (uint32_t)myid, g, sp[sc].nd, sorted, sid, cell_start);
     int32_t cnt = 0;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
@@ -1139,13 +1165,16 @@ __attribute__((amdgpu_waves_per_eu(KMAX <= kLpRegRows ? 3 : 1))) void k_velocity
 // which their projection failed, so that a wave of k_fallback takes agents
 // whose programs start at the same row and follow similar paths.  Order
 // within a key is whatever the LDS atomics give; results do not depend on it.
+// fb_total (profiling, nullable): the pass's fallback count is added to it.
 __global__ __launch_bounds__(kFbSortBlock) void k_fb_sort(const uint8_t *__restrict__ key,
                                                           int32_t *__restrict__ order,
-                                                          const Counters *__restrict__ counters)
+                                                          const Counters *__restrict__ counters,
+                                                          unsigned long long *__restrict__ fb_total)
 {
     constexpr int kPer = kFbSortChunk / kFbSortBlock;
     __shared__ uint32_t hist[64];
     const uint32_t count = counters->n_fallback;
+    if (fb_total && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(fb_total, (unsigned long long)count);
     const uint32_t c0 = blockIdx.x * (uint32_t)kFbSortChunk;
     if (c0 >= count) return;  // uniform over the block
     const uint32_t c1 = min(c0 + (uint32_t)kFbSortChunk, count);
@@ -1631,7 +1660,7 @@ hipError_t launch_fallback_mode(const Plan &pl, hipStream_t st)
     // persistent: fb_waves_per_cu one-wave blocks per CU loop over the device-side list
     const int32_t gs = (pl.n + kFbSortChunk - 1) / kFbSortChunk;
     hipLaunchKernelGGL(k_fb_sort, dim3(gs), dim3(kFbSortBlock), 0, st, pl.fb_key, pl.fb_order,
-                       pl.counters);
+                       pl.counters, pl.fb_total);
     const int32_t gf = max(1, min((pl.n + kLpBlock - 1) / kLpBlock, pl.fb_waves_per_cu * pl.cus));
     if (pl.fb_work_units && KMAX <= kLpRegRows)
         hipLaunchKernelGGL((k_fallback<KMAX, MODE, KMAX <= kLpRegRows>), dim3(gf), dim3(kLpBlock),

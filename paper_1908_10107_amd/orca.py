@@ -298,9 +298,12 @@ class Context:
                                            ptr(g_pref_vel), ptr(g_max_speed),
                                            ptr(g_time_horizon)))
 
-    def profile(self, enable: bool):
-        """Start (clearing the sums) or stop per-stage HIP-event timing."""
-        self._check(self.lib.orca_profile(self.h, int(bool(enable))))
+    def profile(self, enable):
+        """Per-stage HIP-event timing (see orca_profile): 0/False stops, 1/True
+        starts with every pass waiting for its stream, 2 starts without waiting
+        (profile_read then waits); starting clears the sums."""
+        mode = int(enable) if not isinstance(enable, bool) else int(enable)
+        self._check(self.lib.orca_profile(self.h, mode))
 
     def profile_read(self):
         """(stage_ms[4] summed, passes, fallback agents summed); see orca_profile_read."""

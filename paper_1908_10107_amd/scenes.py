@@ -245,11 +245,12 @@ def dense_uniform(n: int = 1 << 20, density: float = 2.0, seed: int = BASE_SEED 
 
 
 def batched(n_scenes: int = 512, seed: int = BASE_SEED + 3, steps: int = 300,
-            n_min: int = 64, n_max: int = 16384) -> Workload:
-    """Independent scenes of log-uniform size with per-scene density, v_max and tau."""
+            n_min: int = 64, n_max: int = 16384, density=(0.3, 2.0)) -> Workload:
+    """Independent scenes of log-uniform size with per-scene density (uniform in
+    ``density``), v_max and tau."""
     rng = np.random.default_rng(seed)
     sizes = np.rint(np.exp(rng.uniform(math.log(n_min), math.log(n_max), n_scenes))).astype(int)
-    dens = rng.uniform(0.3, 2.0, n_scenes)
+    dens = rng.uniform(density[0], density[1], n_scenes)
     vmax = rng.uniform(1.0, 2.0, n_scenes)
     tau = rng.uniform(2.0, 8.0, n_scenes)
     pos_l, goal_l, params = [], [], []

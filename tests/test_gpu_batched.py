@@ -51,6 +51,47 @@ def test_graph_replay_equals_eager():
     cb.close()
 
 
+def test_graph_blocks_equal_eager():
+    """Graph replays of 10-step blocks (resident between their steps) plus
+    single-step replays for the rest equal one eager multi-step call and
+    one-step calls bit for bit, replay after replay, also when the captured
+    graphs are reused by a later call and after the pointers change."""
+    torch = _torch()
+    from paper_1908_10107_amd import orca
+    say("case graph blocks vs eager")
+    w = scenes.batched(n_scenes=30, n_min=64, n_max=3000, seed=13)
+    kmax = max(p.max_neighbors for p in w.params)
+    a = orca.to_device(w)
+    b = {k: (None if v is None else v.clone()) for k, v in a.items()}
+    c = {k: (None if v is None else v.clone()) for k, v in a.items()}
+    ca = orca.Context(max_agents=w.n, max_scenes=w.n_scenes, k_max=kmax)
+    cb = orca.Context(max_agents=w.n, max_scenes=w.n_scenes, k_max=kmax)
+    side = torch.zeros(1 << 20, device="cuda")
+    done = 0
+    for n in (23, 10, 7, 12):
+        ca.step(w.offsets, w.params, a["pos"], a["vel"], a["pref_vel"], goals=a["goals"],
+                n_steps=n)
+        cb.step_graph(w.offsets, w.params, b["pos"], b["vel"], b["pref_vel"], goals=b["goals"],
+                      n_steps=n)
+        side.add_(1.0)           # unrelated eager work between replays
+        torch.cuda.synchronize()
+        done += n
+        for k in ("pos", "vel", "pref_vel"):
+            assert torch.equal(a[k], b[k]), (done, k)
+    # new pointers: the graphs are captured again
+    for k in ("pos", "vel", "pref_vel"):
+        c[k].copy_(b[k])
+    cb.step_graph(w.offsets, w.params, c["pos"], c["vel"], c["pref_vel"], goals=c["goals"],
+                  n_steps=15)
+    for _ in range(15):
+        ca.step(w.offsets, w.params, a["pos"], a["vel"], a["pref_vel"], goals=a["goals"])
+    torch.cuda.synchronize()
+    for k in ("pos", "vel", "pref_vel"):
+        assert torch.equal(a[k], c[k]), k
+    ca.close()
+    cb.close()
+
+
 def test_batched_equals_per_scene():
     torch = _torch()
     from paper_1908_10107_amd import orca

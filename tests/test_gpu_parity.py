@@ -446,6 +446,20 @@ def test_deep_batched():
                 label="batched")
 
 
+def test_deep_batched_dense():
+    """64 scenes packed at 1.8-2.4 agents/m^2 (the random sequential addition
+    limit is about 2.8): every agent checked every 20th step through 100, so
+    the batched path's least-penetration fallback is exercised in many
+    scenes at once."""
+    say("case deep batched dense 64 scenes")
+    w = scenes.batched(n_scenes=64, n_min=64, n_max=4000, seed=scenes.BASE_SEED + 30,
+                       density=(1.8, 2.4))
+    rec = deep_parity(w, [0, 20, 40, 60, 80, 99], label="batched dense")
+    fb = sum(r[3] for r in rec[1:])
+    checked = sum(r[4] for r in rec[1:])
+    assert fb >= 0.1 * checked, (fb, checked)
+
+
 def test_full_size_ring_first_steps():
     """The ring's first three steps, every agent, one step per call."""
     say("case ring 65536 first steps")
