@@ -10,8 +10,9 @@
 //   to vhat_i and to v_max, then through each half-plane to its relative
 //   position P = x_j - x_i, relative velocity V = v_i - v_j, v_i (through
 //   v_i + u/2) and tau;
-//   scatter P and V gradients to agents i and j with float64 atomics into
-//   accumulators indexed by the step's sorted index.
+//   scatter P and V gradients to neighbours j with float64 atomics into
+//   accumulators indexed by the step's sorted index, and store agent i's own
+//   share (summed over its rows) beside them.
 // k_backward_finish then writes dL/dx = dL/dx' + (scattered part), dL/dv
 // (scattered part) by agent id, adds the per-scene v_max and tau gradients,
 // and clears the float64 accumulators for the next use.
@@ -101,10 +102,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             gvix += gVx;
             gviy += gVy;
         }
-        atomicAdd(&a.acc[s], gxi);
-        atomicAdd(&a.acc[n + s], gyi);
-        atomicAdd(&a.acc[2 * n + s], gvix);
-        atomicAdd(&a.acc[3 * n + s], gviy);
+        // the agent's own share: each sorted index is written by its own
+        // lane only, so plain stores beside the neighbours' atomics
+        a.own[s] = gxi;
+        a.own[n + s] = gyi;
+        a.own[2 * n + s] = gvix;
+        a.own[3 * n + s] = gviy;
         a.g_pref[i] += (float)gvhx;
         a.g_pref[n + i] += (float)gvhy;
         if (a.max_speed) gvmax = 0.0;  // the agent's own max speed is a constant here
@@ -130,12 +133,12 @@ __global__ __launch_bounds__(256) void k_backward_finish(BackArgs a)
     const int32_t n = a.n;
     if (s < n) {
         const int32_t i = a.sid[s];
-        const double gx = (double)a.g_pos_next[i] + a.acc[s];
-        const double gy = (double)a.g_pos_next[n + i] + a.acc[n + s];
+        const double gx = (double)a.g_pos_next[i] + (a.own[s] + a.acc[s]);
+        const double gy = (double)a.g_pos_next[n + i] + (a.own[n + s] + a.acc[n + s]);
         a.g_pos[i] = (float)gx;
         a.g_pos[n + i] = (float)gy;
-        a.g_vel[i] = (float)a.acc[2 * n + s];
-        a.g_vel[n + i] = (float)a.acc[3 * n + s];
+        a.g_vel[i] = (float)(a.own[2 * n + s] + a.acc[2 * n + s]);
+        a.g_vel[n + i] = (float)(a.own[3 * n + s] + a.acc[3 * n + s]);
         a.acc[s] = 0.0;
         a.acc[n + s] = 0.0;
         a.acc[2 * n + s] = 0.0;

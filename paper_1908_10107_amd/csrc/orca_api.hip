@@ -101,6 +101,7 @@ struct orca_ctx {
     orca::TapeCode *tape_codes = nullptr;   // [tape_steps, A]
     int32_t *tape_sid = nullptr;            // [tape_steps, A]
     double *acc = nullptr;                  // [4, A]
+    double *own = nullptr;                  // [4, A]
     double *acc_scene = nullptr;            // [2, S]
     int32_t tape_len = 0;                   // steps held by the last recording
     uint64_t tape_scene_version = 0;
@@ -472,6 +473,7 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->sg[1], sizeof(float2) * A) &&
               alloc((void **)&ctx->fb_total, sizeof(unsigned long long)) &&
               alloc((void **)&ctx->acc, sizeof(double) * 4 * A) &&
+              alloc((void **)&ctx->own, sizeof(double) * 4 * A) &&
               alloc((void **)&ctx->acc_scene, sizeof(double) * 2 * S);
     const size_t T = (size_t)tape_steps;
     if (ok && T > 0)
@@ -636,18 +638,22 @@ int orca_step(orca_ctx *ctx, int32_t n_scenes, const int64_t *scene_offsets,
     pl.out.goals = goals;
     ctx->grid_valid = false;
     if (save_tape) ctx->tape_len = 0;
-    // plain steps of a multi-step call run resident (resident_step)
-    const bool resident = n_steps > 1 && !save_tape && !ctx->l_spawn;
+    // the steps of a multi-step call run resident (resident_step), recorded
+    // ones too (not with spawning and removal)
+    const bool resident = n_steps > 1 && !ctx->l_spawn;
     for (int32_t t = 0; t < n_steps; ++t) {
         if (resident) resident_step(ctx, pl, t, n_steps, goals ? goals : pref_vel);
         if (save_tape) {
             // the step's neighbour lists and cell-order ids go straight to
-            // the tape slot; state and choices are written by sorted index
+            // the tape slot (a resident step takes the previous step's ids
+            // from the previous slot); state and choices are written by
+            // sorted index
             const size_t A = (size_t)ctx->max_agents;
             pl.out.tape_state = ctx->tape_state + (size_t)t * A;
             pl.out.tape_codes = ctx->tape_codes + (size_t)t * A;
             pl.nbr = ctx->tape_nbr + (size_t)t * A * (size_t)ctx->k_max;
             pl.sid = ctx->tape_sid + (size_t)t * A;
+            if (resident && t > 0) pl.sid_prev = ctx->tape_sid + (size_t)(t - 1) * A;
         }
         rc = run_pass(ctx, pl, pos, vel);
         if (rc != ORCA_OK) return rc;
@@ -949,6 +955,7 @@ int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
     a.g_max_speed = g_max_speed;
     a.g_time_horizon = g_time_horizon;
     a.acc = ctx->acc;
+    a.own = ctx->own;
     a.acc_scene = ctx->acc_scene;
     a.radius = ctx->tape_radius;
     a.max_speed = ctx->tape_vmax;

@@ -161,6 +161,7 @@ struct BackArgs {
     const float *radius;      // per-agent radii of the recorded step, or nullptr
     const float *max_speed;   // per-agent max speeds of the recorded step, or nullptr
     double *acc;              // [4, n] float64 accumulators by sorted index (kept zero)
+    double *own;              // [4, n] each agent's own share by sorted index
     double *acc_scene;        // [2, n_scenes]
 };
 hipError_t launch_backward(const BackArgs &a, hipStream_t st);
