@@ -43,49 +43,59 @@ struct RowGeom {
     double ux, uy, nx, ny, b;
 };
 
-ORCA_HD inline void row_geom(RowGeom &g, double R, double tau, double dt, double vix, double viy)
+// inv_tau, inv_dt: 1 / tau and 1 / dt rounded to nearest, as the forward step
+// computes them (so the half-plane is the forward's bit for bit).
+ORCA_HD inline void row_geom(RowGeom &g, double R, double tau, double dt, double inv_tau,
+                             double inv_dt, double vix, double viy)
 {
-    obstacle_exit(g.Px, g.Py, g.Vx, g.Vy, R, tau, dt, 1.0 / tau, 1.0 / dt, g.first != 0, g.ux,
+    obstacle_exit(g.Px, g.Py, g.Vx, g.Vy, R, tau, dt, inv_tau, inv_dt, g.first != 0, g.ux,
                   g.uy, g.nx, g.ny);
     const double qx = vix + 0.5 * g.ux, qy = viy + 0.5 * g.uy;
     g.b = g.nx * qx + g.ny * qy;
 }
 
-// Gradient of one obstacle_exit call: (gux, guy, gnx, gny) -> P, V, tau.
+// Gradient of one obstacle_exit call: (gux, guy, gnx, gny) -> P, V, tau.  The
+// branch is the one the recorded half-plane took (the case tests below are
+// the forward's: w from div_recip with inv_tau / inv_dt = 1 / tau, 1 / dt
+// rounded to nearest rounds as the division does); within it, quotients use
+// reciprocals, which moves the gradient by rounding only.
 ORCA_HD inline void obstacle_exit_vjp(const RowGeom &g, double R, double tau, double dt,
-                                      double gux, double guy, double gnx, double gny, double &gPx,
+                                      double inv_tau, double inv_dt, double gux, double guy, double gnx, double gny, double &gPx,
                                       double &gPy, double &gVx, double &gVy, double &gtau)
 {
     const double Px = g.Px, Py = g.Py, Vx = g.Vx, Vy = g.Vy;
     const double dist2 = Px * Px + Py * Py;
     const double R2 = R * R;
     if (dist2 > R2) {
-        const double wx = Vx - Px / tau, wy = Vy - Py / tau;
+        const double wx = Vx - div_recip(Px, tau, inv_tau);
+        const double wy = Vy - div_recip(Py, tau, inv_tau);
         const double w2 = wx * wx + wy * wy;
         const double wP = wx * Px + wy * Py;
         if (wP < 0.0 && wP * wP > R2 * w2) {
             // u = f n with n = w / |w|, f = R / tau - |w|, w = V - P / tau
             const double wl = sqrt(w2);
-            const double nx = wx / wl, ny = wy / wl;
-            const double f = R / tau - wl;
+            const double iw = 1.0 / wl;
+            const double nx = wx * iw, ny = wy * iw;
+            const double f = R * inv_tau - wl;
             const double gf = gux * nx + guy * ny;
             const double gtx = gnx + f * gux, gty = gny + f * guy;
             const double nd = nx * gtx + ny * gty;
-            const double gwx = (gtx - nx * nd) / wl - gf * nx;
-            const double gwy = (gty - ny * nd) / wl - gf * ny;
-            gtau += -gf * R / (tau * tau) + (gwx * Px + gwy * Py) / (tau * tau);
+            const double gwx = (gtx - nx * nd) * iw - gf * nx;
+            const double gwy = (gty - ny * nd) * iw - gf * ny;
+            gtau += (-gf * R + (gwx * Px + gwy * Py)) * (inv_tau * inv_tau);
             gVx += gwx;
             gVy += gwy;
-            gPx += -gwx / tau;
-            gPy += -gwy / tau;
+            gPx += -gwx * inv_tau;
+            gPy += -gwy * inv_tau;
             return;
         }
         // leg: l = A / |P|^2 with A = L P +- R J P, J P = (-Py, Px), L = sqrt(|P|^2 - R^2)
         const bool left = Px * wy - Py * wx > 0.0;
         const double L = sqrt(dist2 - R2);
+        const double id2 = 1.0 / dist2, iL = 1.0 / L;
         const double sg = left ? 1.0 : -1.0;
         const double Ax = Px * L - sg * Py * R, Ay = sg * Px * R + Py * L;
-        const double lx = Ax / dist2, ly = Ay / dist2;
+        const double lx = Ax * id2, ly = Ay * id2;
         double glx, gly;
         if (left) {  // n = (-ly, lx)
             glx = gny;
@@ -102,46 +112,50 @@ ORCA_HD inline void obstacle_exit_vjp(const RowGeom &g, double R, double tau, do
         gVx += gs * lx - gux;
         gVy += gs * ly - guy;
         // l = A / d2
-        const double gAx = glx / dist2, gAy = gly / dist2;
-        const double gd2 = -(glx * lx + gly * ly) / dist2;
+        const double gAx = glx * id2, gAy = gly * id2;
+        const double gd2 = -(glx * lx + gly * ly) * id2;
         // A = L P + sg R J P:  dA = L dP + sg R J dP + P (P . dP) / L
         const double AP = gAx * Px + gAy * Py;
-        gPx += L * gAx + sg * R * gAy + AP * Px / L + 2.0 * gd2 * Px;
-        gPy += L * gAy - sg * R * gAx + AP * Py / L + 2.0 * gd2 * Py;
+        gPx += L * gAx + sg * R * gAy + AP * Px * iL + 2.0 * gd2 * Px;
+        gPy += L * gAy - sg * R * gAx + AP * Py * iL + 2.0 * gd2 * Py;
         return;
     }
     // contact: the one-step disc D(P/dt, R/dt)
-    const double wx = Vx - Px / dt, wy = Vy - Py / dt;
+    const double wx = Vx - div_recip(Px, dt, inv_dt);
+    const double wy = Vy - div_recip(Py, dt, inv_dt);
     const double wl = sqrt(wx * wx + wy * wy);
     if (wl > 0.0) {
-        const double nx = wx / wl, ny = wy / wl;
-        const double f = R / dt - wl;
+        const double iw = 1.0 / wl;
+        const double nx = wx * iw, ny = wy * iw;
+        const double f = R * inv_dt - wl;
         const double gf = gux * nx + guy * ny;
         const double gtx = gnx + f * gux, gty = gny + f * guy;
         const double nd = nx * gtx + ny * gty;
-        const double gwx = (gtx - nx * nd) / wl - gf * nx;
-        const double gwy = (gty - ny * nd) / wl - gf * ny;
+        const double gwx = (gtx - nx * nd) * iw - gf * nx;
+        const double gwy = (gty - ny * nd) * iw - gf * ny;
         gVx += gwx;
         gVy += gwy;
-        gPx += -gwx / dt;
-        gPy += -gwy / dt;
+        gPx += -gwx * inv_dt;
+        gPy += -gwy * inv_dt;
     } else if (dist2 > 0.0) {
         // n = -P / |P|, u = (R / dt) n
         const double pl = sqrt(dist2);
-        const double nx = -Px / pl, ny = -Py / pl;
-        const double f = R / dt;
+        const double ip = 1.0 / pl;
+        const double nx = -Px * ip, ny = -Py * ip;
+        const double f = R * inv_dt;
         const double gtx = gnx + f * gux, gty = gny + f * guy;
         const double nd = nx * gtx + ny * gty;
-        gPx += -(gtx - nx * nd) / pl;
-        gPy += -(gty - ny * nd) / pl;
+        gPx += -(gtx - nx * nd) * ip;
+        gPy += -(gty - ny * nd) * ip;
     }
 }
 
 // Gradient of row r's (n, b) -> P, V, tau and the agent's own velocity v_i
 // (b = n . (v_i + u / 2)).
-ORCA_HD inline void row_vjp(const RowGeom &g, double R, double tau, double dt, double vix,
-                            double viy, double gnx, double gny, double gb, double &gPx, double &gPy,
-                            double &gVx, double &gVy, double &gtau, double &gvix, double &gviy)
+ORCA_HD inline void row_vjp(const RowGeom &g, double R, double tau, double dt, double inv_tau,
+                            double inv_dt, double vix, double viy, double gnx, double gny, double gb,
+                            double &gPx, double &gPy, double &gVx, double &gVy, double &gtau,
+                            double &gvix, double &gviy)
 {
     const double qx = vix + 0.5 * g.ux, qy = viy + 0.5 * g.uy;
     gnx += gb * qx;
@@ -149,7 +163,8 @@ ORCA_HD inline void row_vjp(const RowGeom &g, double R, double tau, double dt, d
     const double gqx = gb * g.nx, gqy = gb * g.ny;
     gvix += gqx;
     gviy += gqy;
-    obstacle_exit_vjp(g, R, tau, dt, 0.5 * gqx, 0.5 * gqy, gnx, gny, gPx, gPy, gVx, gVy, gtau);
+    obstacle_exit_vjp(g, R, tau, dt, inv_tau, inv_dt, 0.5 * gqx, 0.5 * gqy, gnx, gny, gPx, gPy, gVx, gVy,
+                      gtau);
 }
 
 // The rows a record refers to, in fixed slots (the caller fetches them):

@@ -46,6 +46,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         const TapeCode tc = a.codes[s];
         const float4 me = a.state[s];
         const double tau = (double)p.tau, dt = (double)p.dt;
+        const double inv_tau = 1.0 / tau, inv_dt = 1.0 / dt;  // as the forward step has them
         const double ri = (double)(a.radius ? a.radius[i] : p.radius);
         const double vmax = (double)(a.max_speed ? a.max_speed[i] : p.vmax);
         const double vix = (double)me.z, viy = (double)me.w;
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 rows[q].Vy = viy - (double)o.w;
                 rows[q].first = entry >= 0;
                 Rq[q] = ri + (double)(a.radius ? a.radius[a.sid[j]] : p.radius);
-                row_geom(rows[q], Rq[q], tau, dt, vix, viy);
+                row_geom(rows[q], Rq[q], tau, dt, inv_tau, inv_dt, vix, viy);
                 js[q] = j;
             }
         }
@@ -89,8 +90,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int q = 0; q < kSlots; ++q) {
             if (js[q] < 0) continue;
             double gPx = 0.0, gPy = 0.0, gVx = 0.0, gVy = 0.0;
-            row_vjp(rows[q], Rq[q], tau, dt, vix, viy, sg.gnx[q], sg.gny[q], sg.gb[q], gPx, gPy,
-                    gVx, gVy, gtau, gvix, gviy);
+            row_vjp(rows[q], Rq[q], tau, dt, inv_tau, inv_dt, vix, viy, sg.gnx[q], sg.gny[q],
+                    sg.gb[q], gPx, gPy, gVx, gVy, gtau, gvix, gviy);
             const int32_t j = js[q];
             // P = x_j - x_i, V = v_i - v_j
             atomicAdd(&a.acc[j], gPx);
