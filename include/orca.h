@@ -288,6 +288,22 @@ int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
                   float *g_max_speed, float *g_time_horizon);
 
 /*
+ * orca_backward over the recorded steps last, last - 1, ..., first (0 <=
+ * first <= last < the number of recorded steps): g_pos_next / g_vel_next are
+ * the gradients after step last, g_pos / g_vel receive those before step
+ * first, and the preferred-velocity, max_speed and time_horizon gradients of
+ * every step are ADDED as orca_backward adds them.  The same products as
+ * calling orca_backward for each step in turn (equal to float32 rounding of
+ * the accumulation order): between the steps the gradients stay in the
+ * context, one 16-byte entry per agent, so each step reads and writes one
+ * line per agent instead of one per component.  The output arrays may be the
+ * input arrays.  Errors: EINVAL, ESTATE (no such recorded steps), EHIP.
+ */
+int orca_backward_steps(orca_ctx *ctx, int32_t first, int32_t last, const float *g_pos_next,
+                        const float *g_vel_next, float *g_pos, float *g_vel, float *g_pref_vel,
+                        float *g_max_speed, float *g_time_horizon);
+
+/*
  * Diagnostics: per-stage GPU time of every pass (orca_compute_velocities, or
  * one step of orca_step) measured with HIP events recorded on the context
  * stream between the stages.  Stages:

@@ -7,7 +7,7 @@ and the per-scene max speed and time horizon.  Memory is bounded by step
 checkpointing: the forward keeps the state every ``sim.segment`` steps; the
 backward replays each segment from its checkpoint with the steps recorded
 (neighbour ids, half-plane choices and active constraints), then runs the
-hand-written adjoint of each step in reverse (orca_backward).  The forward
+hand-written adjoint of its steps in reverse (orca_backward_steps).  The forward
 records its last segment as it goes, so the backward replays that one only
 if the context has stepped since (a recorded step is bitwise the plain one).
 """
@@ -87,8 +87,7 @@ class OrcaTrajectory(torch.autograd.Function):
                 pos = pos_c.clone()
                 vel = vel_c.clone()
                 lib.step(spec.offsets, params, pos, vel, pref_c, n_steps=k, save_tape=True)
-            for t in reversed(range(k)):
-                lib.backward(t, gp, gv, gp, gv, g_pref, g_vmax, g_tau)
+            lib.backward_steps(0, k - 1, gp, gv, gp, gv, g_pref, g_vmax, g_tau)
         return gp, gv, g_pref, g_vmax, g_tau, None
 
 

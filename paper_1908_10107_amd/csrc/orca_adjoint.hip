@@ -41,7 +41,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     double gvmax = 0.0, gtau = 0.0;
     if (live) {
         const int32_t i = a.sid[s];
-        sc = a.agent_scene[i];
+        // a recorded step's scenes keep their index ranges in cell order
+        sc = a.agent_scene[s];
         const SceneDev p = a.sp[sc];
         const TapeCode tc = a.codes[s];
         const float4 me = a.state[s];
@@ -50,9 +51,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         const double ri = (double)(a.radius ? a.radius[i] : p.radius);
         const double vmax = (double)(a.max_speed ? a.max_speed[i] : p.vmax);
         const double vix = (double)me.z, viy = (double)me.w;
-        const double vhx = (double)a.pref[i], vhy = (double)a.pref[n + i];
-        const double gx = (double)a.g_vel_next[i] + dt * (double)a.g_pos_next[i];
-        const double gy = (double)a.g_vel_next[n + i] + dt * (double)a.g_pos_next[n + i];
+        double vhx, vhy, gx, gy;
+        if (a.pref2) {
+            const float2 ph = a.pref2[i];
+            vhx = (double)ph.x;
+            vhy = (double)ph.y;
+        } else {
+            vhx = (double)a.pref[i];
+            vhy = (double)a.pref[n + i];
+        }
+        if (a.g_in4) {
+            const float4 gn = a.g_in4[i];
+            gx = (double)gn.z + dt * (double)gn.x;
+            gy = (double)gn.w + dt * (double)gn.y;
+        } else {
+            gx = (double)a.g_vel_next[i] + dt * (double)a.g_pos_next[i];
+            gy = (double)a.g_vel_next[n + i] + dt * (double)a.g_pos_next[n + i];
+        }
         int r[kSlots];
         slot_rows(tc, r);
         RowGeom rows[kSlots];
@@ -109,8 +124,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         a.own[n + s] = gyi;
         a.own[2 * n + s] = gvix;
         a.own[3 * n + s] = gviy;
-        a.g_pref[i] += (float)gvhx;
-        a.g_pref[n + i] += (float)gvhy;
+        if (a.g_pref2) {
+            float2 gp = a.g_pref2[i];
+            gp.x += (float)gvhx;
+            gp.y += (float)gvhy;
+            a.g_pref2[i] = gp;
+        } else {
+            a.g_pref[i] += (float)gvhx;
+            a.g_pref[n + i] += (float)gvhy;
+        }
         if (a.max_speed) gvmax = 0.0;  // the agent's own max speed is a constant here
     }
     // per-scene parameters: one atomic per wave when the wave is one scene
@@ -134,12 +156,27 @@ __global__ __launch_bounds__(256) void k_backward_finish(BackArgs a)
     const int32_t n = a.n;
     if (s < n) {
         const int32_t i = a.sid[s];
-        const double gx = (double)a.g_pos_next[i] + (a.own[s] + a.acc[s]);
-        const double gy = (double)a.g_pos_next[n + i] + (a.own[n + s] + a.acc[n + s]);
-        a.g_pos[i] = (float)gx;
-        a.g_pos[n + i] = (float)gy;
-        a.g_vel[i] = (float)(a.own[2 * n + s] + a.acc[2 * n + s]);
-        a.g_vel[n + i] = (float)(a.own[3 * n + s] + a.acc[3 * n + s]);
+        double gpx, gpy;
+        if (a.g_in4) {
+            const float4 gn = a.g_in4[i];
+            gpx = (double)gn.x;
+            gpy = (double)gn.y;
+        } else {
+            gpx = (double)a.g_pos_next[i];
+            gpy = (double)a.g_pos_next[n + i];
+        }
+        const float gx = (float)(gpx + (a.own[s] + a.acc[s]));
+        const float gy = (float)(gpy + (a.own[n + s] + a.acc[n + s]));
+        const float gvx = (float)(a.own[2 * n + s] + a.acc[2 * n + s]);
+        const float gvy = (float)(a.own[3 * n + s] + a.acc[3 * n + s]);
+        if (a.g_out4) {
+            a.g_out4[i] = make_float4(gx, gy, gvx, gvy);
+        } else {
+            a.g_pos[i] = gx;
+            a.g_pos[n + i] = gy;
+            a.g_vel[i] = gvx;
+            a.g_vel[n + i] = gvy;
+        }
         a.acc[s] = 0.0;
         a.acc[n + s] = 0.0;
         a.acc[2 * n + s] = 0.0;
@@ -151,6 +188,43 @@ __global__ __launch_bounds__(256) void k_backward_finish(BackArgs a)
         a.acc_scene[s] = 0.0;
         a.acc_scene[a.n_scenes + s] = 0.0;
     }
+}
+
+__global__ __launch_bounds__(256) void k_backward_prep(const float *__restrict__ pref,
+                                                       float2 *__restrict__ pref2,
+                                                       float2 *__restrict__ g_pref2, int32_t n)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    pref2[i] = make_float2(pref[i], pref[n + i]);
+    g_pref2[i] = make_float2(0.f, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_backward_post(const float2 *__restrict__ g_pref2,
+                                                       float *__restrict__ g_pref, int32_t n)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 g = g_pref2[i];
+    g_pref[i] += g.x;
+    g_pref[n + i] += g.y;
+}
+
+hipError_t launch_backward_prep(const float *pref, float2 *pref2, float2 *g_pref2, int32_t n,
+                                hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_backward_prep, dim3((n + 255) / 256), dim3(256), 0, st, pref, pref2,
+                           g_pref2, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward_post(const float2 *g_pref2, float *g_pref, int32_t n, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_backward_post, dim3((n + 255) / 256), dim3(256), 0, st, g_pref2,
+                           g_pref, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_backward(const BackArgs &a, hipStream_t st)

@@ -102,6 +102,8 @@ struct orca_ctx {
     int32_t *tape_sid = nullptr;            // [tape_steps, A]
     double *acc = nullptr;                  // [4, A]
     double *own = nullptr;                  // [4, A]
+    float4 *g4 = nullptr;                   // [A] gradients between steps (orca_backward_steps)
+    float2 *pref2 = nullptr, *g_pref2 = nullptr;  // [A] each
     double *acc_scene = nullptr;            // [2, S]
     int32_t tape_len = 0;                   // steps held by the last recording
     uint64_t tape_scene_version = 0;
@@ -477,7 +479,10 @@ int orca_create(orca_ctx **out, int64_t max_agents, int32_t max_scenes, int32_t 
               alloc((void **)&ctx->acc_scene, sizeof(double) * 2 * S);
     const size_t T = (size_t)tape_steps;
     if (ok && T > 0)
-        ok = alloc((void **)&ctx->tape_state, sizeof(float4) * T * A) &&
+        ok = alloc((void **)&ctx->g4, sizeof(float4) * A) &&
+             alloc((void **)&ctx->pref2, sizeof(float2) * A) &&
+             alloc((void **)&ctx->g_pref2, sizeof(float2) * A) &&
+             alloc((void **)&ctx->tape_state, sizeof(float4) * T * A) &&
              alloc((void **)&ctx->tape_nbr, sizeof(int32_t) * T * A * (size_t)k_max) &&
              alloc((void **)&ctx->tape_codes, sizeof(orca::TapeCode) * T * A) &&
              alloc((void **)&ctx->tape_sid, sizeof(int32_t) * T * A);
@@ -923,18 +928,16 @@ int orca_profile_read(orca_ctx *ctx, double *stage_ms, int64_t *passes, int64_t 
     return ORCA_OK;
 }
 
-int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
-                  const float *g_vel_next, float *g_pos, float *g_vel, float *g_pref_vel,
-                  float *g_max_speed, float *g_time_horizon)
+}  // extern "C"
+
+namespace {
+
+// Arguments of the adjoint of recorded step tape_step (agent-order [2, N]
+// gradient arrays; the caller sets the by-id buffers of a run of steps).
+orca::BackArgs back_args(const orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
+                         const float *g_vel_next, float *g_pos, float *g_vel, float *g_pref_vel,
+                         float *g_max_speed, float *g_time_horizon)
 {
-    if (!ctx) return ORCA_EINVAL;
-    if (tape_step < 0 || tape_step >= ctx->tape_len)
-        return fail(ctx, ORCA_ESTATE, "no recorded step %d (the last recording holds %d)",
-                    tape_step, ctx->tape_len);
-    if (ctx->tape_scene_version != ctx->scene_version)
-        return fail(ctx, ORCA_ESTATE, "the scene set changed since the steps were recorded");
-    if (ctx->n > 0 && (!g_pos_next || !g_vel_next || !g_pos || !g_vel || !g_pref_vel))
-        return fail(ctx, ORCA_EINVAL, "gradient arrays must be non-NULL");
     const size_t A = (size_t)ctx->max_agents;
     orca::BackArgs a{};
     a.n = (int32_t)ctx->n;
@@ -959,7 +962,63 @@ int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
     a.acc_scene = ctx->acc_scene;
     a.radius = ctx->tape_radius;
     a.max_speed = ctx->tape_vmax;
+    return a;
+}
+
+int check_backward(orca_ctx *ctx, int32_t first, int32_t last, const float *g_pos_next,
+                   const float *g_vel_next, const float *g_pos, const float *g_vel,
+                   const float *g_pref_vel)
+{
+    if (first < 0 || last < first || last >= ctx->tape_len)
+        return fail(ctx, ORCA_ESTATE, "no recorded steps %d..%d (the last recording holds %d)",
+                    first, last, ctx->tape_len);
+    if (ctx->tape_scene_version != ctx->scene_version)
+        return fail(ctx, ORCA_ESTATE, "the scene set changed since the steps were recorded");
+    if (ctx->n > 0 && (!g_pos_next || !g_vel_next || !g_pos || !g_vel || !g_pref_vel))
+        return fail(ctx, ORCA_EINVAL, "gradient arrays must be non-NULL");
+    return ORCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int orca_backward(orca_ctx *ctx, int32_t tape_step, const float *g_pos_next,
+                  const float *g_vel_next, float *g_pos, float *g_vel, float *g_pref_vel,
+                  float *g_max_speed, float *g_time_horizon)
+{
+    if (!ctx) return ORCA_EINVAL;
+    int rc = check_backward(ctx, tape_step, tape_step, g_pos_next, g_vel_next, g_pos, g_vel,
+                            g_pref_vel);
+    if (rc != ORCA_OK) return rc;
+    const orca::BackArgs a = back_args(ctx, tape_step, g_pos_next, g_vel_next, g_pos, g_vel,
+                                       g_pref_vel, g_max_speed, g_time_horizon);
     HIP_OK(orca::launch_backward(a, ctx->stream));
+    return ORCA_OK;
+}
+
+int orca_backward_steps(orca_ctx *ctx, int32_t first, int32_t last, const float *g_pos_next,
+                        const float *g_vel_next, float *g_pos, float *g_vel, float *g_pref_vel,
+                        float *g_max_speed, float *g_time_horizon)
+{
+    if (!ctx) return ORCA_EINVAL;
+    int rc = check_backward(ctx, first, last, g_pos_next, g_vel_next, g_pos, g_vel, g_pref_vel);
+    if (rc != ORCA_OK) return rc;
+    const int32_t n = (int32_t)ctx->n;
+    // the gradients between the steps stay one float4 per agent id in g4
+    // (each step reads and then writes each id's entry), the preferred
+    // velocities and their gradient one float2 per agent id
+    HIP_OK(orca::launch_backward_prep(ctx->tape_pref, ctx->pref2, ctx->g_pref2, n, ctx->stream));
+    for (int32_t t = last; t >= first; --t) {
+        orca::BackArgs a = back_args(ctx, t, g_pos_next, g_vel_next, g_pos, g_vel, g_pref_vel,
+                                     g_max_speed, g_time_horizon);
+        a.pref2 = ctx->pref2;
+        a.g_pref2 = ctx->g_pref2;
+        a.g_in4 = t == last ? nullptr : ctx->g4;
+        a.g_out4 = t == first ? nullptr : ctx->g4;
+        HIP_OK(orca::launch_backward(a, ctx->stream));
+    }
+    HIP_OK(orca::launch_backward_post(ctx->g_pref2, g_pref_vel, n, ctx->stream));
     return ORCA_OK;
 }
 

@@ -162,8 +162,20 @@ struct BackArgs {
     const float *max_speed;   // per-agent max speeds of the recorded step, or nullptr
     double *acc;              // [4, n] float64 accumulators by sorted index (kept zero)
     double *own;              // [4, n] each agent's own share by sorted index
+    // several steps in a row (orca_backward_steps): the gradients between
+    // steps as one float4 (dL/dx, dL/dv) per agent id, the preferred
+    // velocities and their gradient as float2 per agent id (one line per
+    // agent instead of one per component); nullptr: the [2, n] arrays above
+    const float4 *g_in4;      // dL/dx', dL/dv_next by id
+    float4 *g_out4;           // dL/dx, dL/dv by id (may be g_in4: read then written per id)
+    const float2 *pref2;
+    float2 *g_pref2;          // accumulated
     double *acc_scene;        // [2, n_scenes]
 };
 hipError_t launch_backward(const BackArgs &a, hipStream_t st);
+// pref [2, n] -> pref2, g_pref2 cleared (before a run of steps); g_pref [2, n] += g_pref2 (after)
+hipError_t launch_backward_prep(const float *pref, float2 *pref2, float2 *g_pref2, int32_t n,
+                                hipStream_t st);
+hipError_t launch_backward_post(const float2 *g_pref2, float *g_pref, int32_t n, hipStream_t st);
 
 }  // namespace orca

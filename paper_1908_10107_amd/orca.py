@@ -76,6 +76,8 @@ def load(path: str = LIB_PATH):
     L.orca_step.restype = ctypes.c_int
     L.orca_backward.argtypes = [_P, ctypes.c_int32] + [_P] * 7
     L.orca_backward.restype = ctypes.c_int
+    L.orca_backward_steps.argtypes = [_P, ctypes.c_int32, ctypes.c_int32] + [_P] * 7
+    L.orca_backward_steps.restype = ctypes.c_int
     L.orca_step_graph.argtypes = [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_int32]
     L.orca_step_graph.restype = ctypes.c_int
     L.orca_autotune.argtypes = [_P, _P, _P, _P, _P, _P, ctypes.c_int32, _P]
@@ -297,6 +299,23 @@ class Context:
                                            ptr(g_vel_next), ptr(g_pos), ptr(g_vel),
                                            ptr(g_pref_vel), ptr(g_max_speed),
                                            ptr(g_time_horizon)))
+
+    def backward_steps(self, first, last, g_pos_next, g_vel_next, g_pos, g_vel, g_pref_vel,
+                       g_max_speed=None, g_time_horizon=None):
+        """Adjoint of recorded steps last .. first (see orca_backward_steps)."""
+        n = g_pos.shape[1]
+        for t, nm in ((g_pos_next, "g_pos_next"), (g_vel_next, "g_vel_next"), (g_pos, "g_pos"),
+                      (g_vel, "g_vel"), (g_pref_vel, "g_pref_vel")):
+            _dev_ptr(t, nm, n)
+        for t, nm in ((g_max_speed, "g_max_speed"), (g_time_horizon, "g_time_horizon")):
+            if t is not None:
+                _dev_ptr(t, nm, shape2=False)
+        self._sync_stream()
+        ptr = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+        self._check(self.lib.orca_backward_steps(self.h, int(first), int(last), ptr(g_pos_next),
+                                                 ptr(g_vel_next), ptr(g_pos), ptr(g_vel),
+                                                 ptr(g_pref_vel), ptr(g_max_speed),
+                                                 ptr(g_time_horizon)))
 
     def profile(self, enable):
         """Per-stage HIP-event timing (see orca_profile): 0/False stops, 1/True

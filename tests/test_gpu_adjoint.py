@@ -254,3 +254,62 @@ def test_adjoint_against_central_differences(horizon):
     say("  %d of %d directions keep every float64 decision at +-h, worst relative difference "
         "%.2e" % (counted, len(dirs), worst))
     assert counted >= (18 if horizon == 2 else 9)
+
+
+@pytest.mark.parametrize("case", ["plain", "hetero"])
+def test_backward_steps_equals_per_step_backward(case):
+    """orca_backward_steps over a recorded segment (gradients kept per agent id
+    inside the context between the steps) equals orca_backward step by step
+    (gradients through the caller's arrays), to float32 rounding of the
+    accumulation order, with the output arrays aliasing the inputs; a
+    single-step range equals orca_backward."""
+    torch = _torch()
+    from paper_1908_10107_amd import orca
+    say("case backward_steps", case)
+    w = moving_scene(5000, 2.0, 44)
+    if case == "hetero":
+        rng = np.random.default_rng(45)
+        w.radius = rng.choice(np.array([0.15, 0.25, 0.4], np.float32), w.n)
+        w.max_speed = rng.uniform(0.9, 2.0, w.n).astype(np.float32)
+    d = orca.to_device(w)
+    k = w.params[0].max_neighbors
+    steps = 7
+    ctx = orca.Context(max_agents=w.n, max_scenes=1, k_max=k, tape_steps=steps)
+    ctx.set_agents(d["radius"], d["max_speed"])
+    ctx.step(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], n_steps=steps, save_tape=True)
+    rng = np.random.default_rng(46)
+    gp0 = torch.from_numpy(rng.normal(size=(2, w.n)).astype(np.float32)).cuda()
+    gv0 = torch.from_numpy(rng.normal(size=(2, w.n)).astype(np.float32)).cuda()
+    outs = []
+    for mode in ("steps", "each"):
+        gp, gv = gp0.clone(), gv0.clone()
+        gpref = torch.zeros_like(gp)
+        gvm = torch.zeros(1, device="cuda")
+        gta = torch.zeros(1, device="cuda")
+        if mode == "steps":
+            ctx.backward_steps(0, steps - 1, gp, gv, gp, gv, gpref, gvm, gta)
+        else:
+            for t in reversed(range(steps)):
+                ctx.backward(t, gp, gv, gp, gv, gpref, gvm, gta)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy().astype(np.float64) for x in (gp, gv, gpref, gvm, gta)])
+    for name, a, b in zip(("g_pos", "g_vel", "g_pref", "g_vmax", "g_tau"), *outs):
+        scale = max(np.abs(b).max(), 1e-30)
+        err = np.abs(a - b).max() / scale
+        say("  %s: max |steps - each| / max |each| = %.2e" % (name, err))
+        assert err <= 1e-5, (name, err)
+    # a range of one step is orca_backward
+    gp1, gv1 = gp0.clone(), gv0.clone()
+    gp2, gv2 = gp0.clone(), gv0.clone()
+    z = [torch.zeros_like(gp0) for _ in range(2)]
+    ctx.backward_steps(steps - 1, steps - 1, gp1, gv1, gp1, gv1, z[0])
+    ctx.backward(steps - 1, gp2, gv2, gp2, gv2, z[1])
+    torch.cuda.synchronize()
+    for a, b in ((gp1, gp2), (gv1, gv2), (z[0], z[1])):
+        a, b = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+        assert np.abs(a - b).max() <= 1e-5 * max(np.abs(b).max(), 1e-30)
+    with pytest.raises(orca.OrcaError):
+        ctx.backward_steps(3, 2, gp1, gv1, gp1, gv1, z[0])
+    with pytest.raises(orca.OrcaError):
+        ctx.backward_steps(0, steps, gp1, gv1, gp1, gv1, z[0])
+    ctx.close()
