@@ -679,9 +679,10 @@ __device__ __forceinline__ int32_t knn_entry(const uint64_t (&best)[KMAX], int k
 }
 
 // K nearest of each agent (sorted order s), as knn_search finds them (the
-// same search, written out: this kernel keeps the registers of six waves per
-// SIMD only in this form).  Writes nbr[k * ld + s] (entries as knn_entry
-// gives them) and ncount[s].
+// candidates from knn_rows).  Writes nbr[k * ld + s] (entries as knn_entry
+// gives them) and ncount[s].  Held to the registers of six waves per SIMD up
+// to K = 16 (a few bytes of spill at K = 16): the search waits on its
+// candidate gathers, which the sixth wave covers.
 #ifndef ORCA_KNN_WAVES
 #define ORCA_KNN_WAVES 6
 #endif

@@ -147,3 +147,37 @@ def test_autotune_keeps_results():
     with pytest.raises(RuntimeError):
         ctx.set_launch(256, 0)
     ctx.close()
+
+
+def test_profile_modes_agree():
+    """The two timing modes of orca_profile over the same steps: mode 2 (events
+    recorded without waiting, fallback agents counted on the device) gives the
+    fallback count that mode 1 (every pass waits, counts read on the host)
+    gives, and stage times that are positive and sum to at most the wall time
+    of the steps."""
+    torch = _torch()
+    import time
+    from paper_1908_10107_amd import orca
+    say("case profile modes")
+    w = scenes.dense_uniform(n=60000, seed=scenes.BASE_SEED + 50)
+    res = []
+    for mode in (1, 2):
+        d = orca.to_device(w)
+        with orca.Context(max_agents=w.n, max_scenes=1, k_max=16) as ctx:
+            ctx.step(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], goals=d["goals"],
+                     n_steps=3)
+            torch.cuda.synchronize()
+            ctx.profile(mode)
+            t0 = time.perf_counter()
+            ctx.step(w.offsets, w.params, d["pos"], d["vel"], d["pref_vel"], goals=d["goals"],
+                     n_steps=12)
+            ms, passes, fb = ctx.profile_read()
+            torch.cuda.synchronize()
+            wall = 1e3 * (time.perf_counter() - t0)
+            ctx.profile(0)
+        say("  mode %d: stages %s ms, %d passes, %d fallback agents, %.2f ms wall"
+            % (mode, [round(x, 3) for x in ms], passes, fb, wall))
+        assert passes == 12
+        assert all(x > 0 for x in ms) and sum(ms) <= wall
+        res.append(fb)
+    assert res[0] == res[1] and res[0] > 0
