@@ -164,14 +164,17 @@ def host_cpu():
     return dict(nproc=os.cpu_count(), usable=usable, model=model)
 
 
-def cpu_baseline(w, min_seconds: float):
+def cpu_baseline(w, min_seconds: float, evolved=None):
     """The reference (float64 C, OpenMP over agents) on the host's cores.
 
     value: whole steps of the timed workload from its initial state (binning,
     velocities, Euler, steering), stepped one at a time until ``min_seconds``
-    have passed, on every thread.  Also: one thread on a 100,000-agent sample
-    of the same state; the 1,024-agent square's whole 100-step run; the
-    4,096-agent 200-step trajectory with its forward-mode derivative."""
+    have passed, on every thread.  Also: three whole steps from the GPU's
+    state at the end of the timed steps (``evolved``: pos, vel, pref_vel, the
+    crowd the GPU figure was measured on); one thread on a 100,000-agent
+    sample of the initial state; the 1,024-agent square's whole 100-step
+    run; the 4,096-agent 200-step trajectory with its forward-mode
+    derivative."""
     import oracle
     from paper_1908_10107_amd import scenes
     threads = oracle.threads()
@@ -187,6 +190,14 @@ def cpu_baseline(w, min_seconds: float):
     out = dict(value=w.n * steps / dt, unit="agent-steps/s", cores=threads, kind="oracle",
                sample="%d whole steps of all %d agents from the initial state, %.1f s"
                       % (steps, w.n, dt), host=host_cpu())
+    if evolved is not None:
+        pos, vel, pref = evolved
+        t0 = time.perf_counter()
+        oracle.step(pos, vel, pref, w.offsets, w.params, goals=w.goals, n_steps=3)
+        de = time.perf_counter() - t0
+        out["evolved"] = dict(value=w.n * 3 / de, unit="agent-steps/s", cores=threads,
+                              sample="3 whole steps of all %d agents from the GPU's state after "
+                                     "the timed steps, %.1f s" % (w.n, de))
     # one thread, velocities of a sample of the same initial state
     rng = np.random.default_rng(1)
     m = min(w.n, 100000)
@@ -488,6 +499,7 @@ def main():
     dom = int(np.argmax(avg))
     # cells of the grid at the end of the timed steps (the 12 B/cell term is small)
     state_now = dataclasses.replace(w, pos=st["pos"].cpu().numpy())
+    evolved = (st["pos"].cpu().numpy(), st["vel"].cpu().numpy(), st["pref"].cpu().numpy())
     cells = grid_cells(state_now)
     stages = {orca.STAGE_NAMES[i]: round(avg[i], 4) for i in range(orca.PROF_STAGES)}
     bound, achieved, peak, unit = stage_roofline(dom, avg[dom], w.n, kmax, cells, fb_avg)
@@ -549,7 +561,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_seconds)
+        cpu = cpu_baseline(w, args.cpu_seconds, evolved)
 
     line = {
         "metric": METRIC, "value": value, "unit": "agent-steps/s", "n_gpus": 1,
