@@ -109,3 +109,36 @@ def test_noalloc_rejects_sizes_beyond_its_scratch():
     rc = lib.orca_step_noalloc(10, orca.params_array([p]), None, None, None, None, 0, None, err,
                                len(err))
     assert rc == orca.EINVAL
+
+
+def test_noalloc_under_graph_capture():
+    """The entry point enqueues kernels only, so it can be captured into a HIP
+    graph: replays of a captured 4-step call, with eager work and waits
+    between them, equal the same steps run eagerly, replay after replay."""
+    torch = _torch()
+    from paper_1908_10107_amd import orca
+    w = scenes.uniform_rsa()
+    p = w.params[0]
+    say("no-alloc under graph capture: %d agents" % w.n)
+    a = orca.to_device(w)
+    b = orca.to_device(w)
+    orca.step_noalloc(p, a["pos"], a["vel"], a["pref_vel"], goals=a["goals"])  # warm-up
+    orca.step_noalloc(p, b["pos"], b["vel"], b["pref_vel"], goals=b["goals"])
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            orca.step_noalloc(p, b["pos"], b["vel"], b["pref_vel"], goals=b["goals"], n_steps=4)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    # capture does not run the steps: b is still one step in
+    side = torch.zeros(1 << 20, device="cuda")
+    for r in range(3):
+        orca.step_noalloc(p, a["pos"], a["vel"], a["pref_vel"], goals=a["goals"], n_steps=4)
+        g.replay()
+        side.add_(1.0)
+        torch.cuda.synchronize()
+        for k in ("pos", "vel", "pref_vel"):
+            assert torch.equal(a[k], b[k]), (r, k)
