@@ -107,20 +107,29 @@ def profiled_lane_use():
     return out or None
 
 
-def grid_cells(w, cells_per_nd=2, margin=1.0 + 1.0 / 1024.0):
+def grid_cells(w, margin=1.0 + 1.0 / 1024.0):
     """Grid cells of the current positions: per scene, cells of side
-    neighbor_dist * margin / cells_per_nd over the bounding box."""
+    neighbor_dist * margin / c over the bounding box, with the library's
+    choice of c = 2, 3 or 4 cells per neighbor_dist (the 3 x 3 cells around an
+    agent hold about 2.75 K agents at the scene's mean density)."""
     c = 0
+    per_nd = {}
     for s, p in enumerate(w.params):
         lo, hi = int(w.offsets[s]), int(w.offsets[s + 1])
         if hi <= lo:
             c += 1
             continue
         x = w.pos[:, lo:hi].astype(np.float64)
-        side = float(np.float32(p.neighbor_dist)) * margin / cells_per_nd
+        nd = float(np.float32(p.neighbor_dist))
         ext = x.max(axis=1) - x.min(axis=1)
+        cpn = 2
+        if p.max_neighbors > 0:
+            rho = (hi - lo) / max(ext[0] * ext[1], nd * nd)
+            cpn = int(min(max(np.rint(nd * np.sqrt(9.0 * rho / (2.75 * p.max_neighbors))), 2), 4))
+        side = nd * margin / cpn
         c += int((np.floor(ext[0] / side) + 1) * (np.floor(ext[1] / side) + 1))
-    return c
+        per_nd[cpn] = per_nd.get(cpn, 0) + 1
+    return c, per_nd
 
 
 def apply_launch(ctx, launch):
@@ -500,7 +509,7 @@ def main():
     # cells of the grid at the end of the timed steps (the 12 B/cell term is small)
     state_now = dataclasses.replace(w, pos=st["pos"].cpu().numpy())
     evolved = (st["pos"].cpu().numpy(), st["vel"].cpu().numpy(), st["pref"].cpu().numpy())
-    cells = grid_cells(state_now)
+    cells, cells_per_nd = grid_cells(state_now)
     stages = {orca.STAGE_NAMES[i]: round(avg[i], 4) for i in range(orca.PROF_STAGES)}
     bound, achieved, peak, unit = stage_roofline(dom, avg[dom], w.n, kmax, cells, fb_avg)
     others = {}
@@ -571,8 +580,9 @@ def main():
         "config": {"workload": args.workload, "agents": w.n, "scenes": w.n_scenes,
                    "max_neighbors": kmax,
                    "neighbor_dist": w.params[0].neighbor_dist,
-                   "cell": "neighbor_dist * (1 + 2^-10) / 2 (two cells per neighbor_dist; "
-                           "same neighbours as cells of neighbor_dist)",
+                   "cell": "neighbor_dist * (1 + 2^-10) / c, c = 2, 3 or 4 per scene from its "
+                           "density and K (same neighbours as cells of neighbor_dist); scenes "
+                           "per c: " + ", ".join(f"c = {k}: {v}" for k, v in sorted(cells_per_nd.items())),
                    "state": "f32", "lp": "f64", "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -3,9 +3,10 @@
  *
  * One timestep of optimal reciprocal collision avoidance as described in
  * Charlton et al., "Fast Simulation of Crowd Collision Avoidance":
- *   - agents are binned into a uniform grid of square cells half as wide as
- *     the observation radius (section 3, Fig. 2: messages sorted into
- *     spatial bins, each agent reading its own and the nearby bins);
+ *   - agents are binned into a uniform grid of square cells a half, a third
+ *     or a quarter as wide as the observation radius (section 3, Fig. 2:
+ *     messages sorted into spatial bins, each agent reading its own and the
+ *     nearby bins);
  *   - each agent keeps the K nearest others closer than the observation
  *     radius (Fig. 2's radius filter; the cap K is the memory remedy of
  *     section 5);
@@ -110,9 +111,11 @@ int orca_set_stream(orca_ctx *ctx, void *hip_stream);
 /*
  * Bin the agents (section 3, Fig. 2).  pos: device [2, N] with
  * N = scene_offsets[n_scenes].  Per scene: bounding box, cells of side
- * neighbor_dist * (1 + 2^-10) / 2, so a neighbour search reads the cells
- * within two of its own (wider cells if the context's cell budget would be
- * exceeded), cell keys, a counting sort of the agents into cell order.
+ * neighbor_dist * (1 + 2^-10) / c with c = 2, 3 or 4 chosen from the
+ * scene's mean density and K (so the 3 x 3 cells around an agent hold about
+ * 2.75 K agents; a neighbour search reads the cells within c of its own),
+ * wider cells if the context's cell budget would be exceeded, cell keys, a
+ * counting sort of the agents into cell order.
  * The grid stays valid for orca_compute_velocities on the same pos pointer
  * until orca_step or another orca_build_grid.
  * Errors: EINVAL, ECAPACITY (N > max_agents, n_scenes > max_scenes,

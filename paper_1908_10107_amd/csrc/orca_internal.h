@@ -14,8 +14,9 @@ constexpr int kScanTile = kScanItems * kScanBlock;  // cells per scan tile
 constexpr int kLpBlock = 64;                        // one wave per LP block
 constexpr int kBboxChunk = 8192;                    // agents per bounding-box block
 constexpr int kBboxBlock = 1024;                    // threads per bounding-box block
-constexpr double kCellMargin = 1.0 + 1.0 / 1024.0;  // cell side / (neighbor_dist / kCellsPerNd)
-constexpr int kCellsPerNd = 2;                      // grid cells across one neighbor_dist
+constexpr double kCellMargin = 1.0 + 1.0 / 1024.0;  // cell side / (neighbor_dist / cells per nd)
+constexpr int kMinCellsPerNd = 2;                   // grid cells across one neighbor_dist: 2 ..
+constexpr int kMaxCellsPerNd = 4;                   // .. 4, per scene (k_grid)
 constexpr int kFbSortChunk = 4096;                  // fallback slots sorted together
 constexpr int kFbSortBlock = 1024;                  // threads per fallback-sort block (4 slots each)
 

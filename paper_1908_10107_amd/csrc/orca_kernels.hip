@@ -181,10 +181,11 @@ __global__ __launch_bounds__(kBboxBlock) void k_bbox(const float *__restrict__ p
     }
 }
 
-// Grid of every scene.  Cells are square, neighbor_dist * (1 + 2^-10) / 2
-// wide, so two agents closer than neighbor_dist (also after float32 rounding
-// of their squared distance) always sit within two cells of each other in x
-// and in y (the neighbour search reads the disc's chords over them).  If the
+// Grid of every scene.  Cells are square, neighbor_dist * (1 + 2^-10) / c
+// wide with c = 2, 3 or 4 cells per neighbor_dist chosen per scene from its
+// density and K, so two agents closer than neighbor_dist (also after float32
+// rounding of their squared distance) always sit within c cells of each other
+// in x and in y (the neighbour search reads the disc's chords over them).  If the
 // total number of cells would exceed the budget, all cells are widened by a
 // common factor (more candidates per agent, same neighbours).  With spawning
 // and removal on (life), one more cell after all scenes' cells takes the
@@ -208,7 +209,20 @@ __global__ __launch_bounds__(256) void k_grid(int32_t n_scenes, const int32_t *_
             const float x1 = float_from_ord(bbox[4 * s + 2]);
             const float y1 = float_from_ord(bbox[4 * s + 3]);
             const double ex = (double)x1 - (double)x0, ey = (double)y1 - (double)y0;
-            g.cell = (double)sp[s].nd * kCellMargin * f / (double)kCellsPerNd;
+            // cells per neighbor_dist: the 3 x 3 cells around an agent, which the
+            // neighbour search reads first, should hold about 2.75 K agents at the
+            // scene's mean density (fewer and the list is not full after them,
+            // more and they are read for nothing): 2 for sparse crowds or large
+            // K, up to 4 for dense crowds with a long neighbor_dist
+            const double nd = (double)sp[s].nd;
+            int32_t cpn = kMinCellsPerNd;
+            if (sp[s].k > 0 && isfinite(ex) && isfinite(ey)) {
+                const double area = fmax(ex * ey, nd * nd);
+                const double rho = (double)(off[s + 1] - off[s]) / area;
+                const double c = rint(nd * sqrt(9.0 * rho / (2.75 * (double)sp[s].k)));
+                cpn = (int32_t)fmin(fmax(c, (double)kMinCellsPerNd), (double)kMaxCellsPerNd);
+            }
+            g.cell = nd * kCellMargin * f / (double)cpn;
             const bool ok = off[s + 1] > off[s] && isfinite(ex) && isfinite(ey) && ex >= 0.0 &&
                             ey >= 0.0 && iter < 23;
             if (ok) {
@@ -561,21 +575,19 @@ __device__ __forceinline__ void knn_run(uint64_t (&best)[KMAX], uint32_t &lim, u
 // Offer every candidate within reach of an agent (me, id myid, its cell's grid
 // g, float32 neighbor_dist ndf) to its sorted key list, each row of cells over
 // the run its chord of the disc touches (one contiguous run of sorted
-// indices).  Cells are about nd/2 wide, so the disc of radius nd reaches two
-// rows and columns out (one once the grid was widened to nd).  The chords are
-// taken a little wider than the radius, so rounding of the cell arithmetic
-// or of the float32 distance never drops a neighbour: the distance test
-// decides.
+// indices).  Cells are about nd/c wide (c = 2, 3 or 4, per scene), so the
+// disc of radius nd reaches c rows and columns out (fewer once the grid was
+// widened).  The chords are taken a little wider than the radius, so
+// rounding of the cell arithmetic or of the float32 distance never drops a
+// neighbour: the distance test decides.
 //
-// Order: first the 3 x 3 cells around the agent's own (about nd wide, so
-// they hold the K nearest in all but sparse crowds), then the rest, with each
-// chord cut to the list's current limit (the K-th distance once the list is
-// full): the list fills with near candidates first and the outer cells offer
-// few, which a wave would otherwise pay for with an insertion whenever any of
-// its lanes inserts.  The set that can enter is the same, so the result is.
-#ifndef ORCA_KNN_ORDER
-#define ORCA_KNN_ORDER 1
-#endif
+// Order: first the 3 x 3 cells around the agent's own (k_grid sizes cells so
+// that they hold about 2.75 K agents at the scene's mean density, enough for
+// the K nearest), then the rest, with each chord cut to the list's current
+// limit (the K-th distance once the list is full): the list fills with near
+// candidates first and the outer cells offer few, which a wave would
+// otherwise pay for with an insertion whenever any of its lanes inserts.  The
+// set that can enter is the same, so the result is.
 template <int KMAX>
 __device__ __forceinline__ void knn_rows(uint64_t (&best)[KMAX], uint32_t &lim, uint32_t nd_lim,
                                          float4 me, uint32_t myid, const GridDev &g, float ndf,
@@ -587,31 +599,29 @@ __device__ __forceinline__ void knn_rows(uint64_t (&best)[KMAX], uint32_t &lim, 
     cell_of(g, me.x, me.y, cx, cy);
     const double cell = g.cell, nd = (double)ndf;
     // rows and columns the disc of radius nd can reach: nd / cell rounded up
-    // (cells are a little wider than nd / kCellsPerNd, or wider still once the
-    // grid was widened)
-    const int32_t reach = max(1, min(kCellsPerNd, (int32_t)ceil(nd / cell)));
+    // (cells are a little wider than nd / c, or wider still once the grid was
+    // widened)
+    const int32_t reach = max(1, min(kMaxCellsPerNd, (int32_t)ceil(nd / cell)));
     const double px = (double)me.x, py = (double)me.y;
     const double slack = 1e-9 * (1.0 + fabs(px) + fabs(py));
     // segments (one knn_run call site keeps the registers of one row loop):
-    // ORCA_KNN_ORDER 1: 0-2 the inner three columns of rows 0, -1, +1 over
-    // the full chord; 3-8 the columns left and right of them in the same rows
-    // and 9-10 rows -2, +2, over chords cut to the list's current limit.
-    // ORCA_KNN_ORDER 0: rows 0, -1, +1, -2, +2 over their full chords.
-    constexpr int32_t kSegs = ORCA_KNN_ORDER ? 11 : 5;
+    // 0-2 the inner three columns of rows 0, -1, +1 over the full chord;
+    // 3-8 the columns left and right of them in the same rows, and 9-14 rows
+    // -2, +2, -3, +3, -4, +4 (those within reach), over chords cut to the
+    // list's current limit.
+    constexpr int32_t kSegs = 9 + 2 * (kMaxCellsPerNd - 1);
 #pragma unroll 1
     for (int32_t q = 0; q < kSegs; ++q) {
-        int32_t qr = q, part = 0;  // row code, and 0 whole / 1 inner / 2 left / 3 right
-        if (ORCA_KNN_ORDER) {
-            qr = q < 3 ? q : (q < 9 ? (q - 3) >> 1 : q - 6);
-            part = q < 3 ? 1 : (q < 9 ? 2 + ((q - 3) & 1) : 0);
-        }
-        const int32_t dy = (qr & 1) ? -((qr + 1) >> 1) : (qr >> 1);  // 0, -1, +1, -2, +2
+        // row code (dy = 0, -1, +1, -2, +2, ...) and part: 1 inner, 2 left,
+        // 3 right, 0 the whole chord
+        const int32_t qr = q < 3 ? q : (q < 9 ? (q - 3) >> 1 : q - 6);
+        const int32_t part = q < 3 ? 1 : (q < 9 ? 2 + ((q - 3) & 1) : 0);
+        const int32_t dy = (qr & 1) ? -((qr + 1) >> 1) : (qr >> 1);
         if (dy > reach || -dy > reach) continue;
         const int32_t row = cy + dy;
         if (row < 0 || row >= g.ny) continue;
         // the chord's radius: nd, or the list's current limit after the inner cells
-        const double r = (ORCA_KNN_ORDER && part != 1)
-                             ? fmin(nd, sqrt((double)__uint_as_float(lim))) : nd;
+        const double r = part != 1 ? fmin(nd, sqrt((double)__uint_as_float(lim))) : nd;
         const double rx = r * (1.0 + 1e-6) + slack;
         double dyc = 0.0;  // distance from the agent to the row's band in y
         if (dy > 0) dyc = fmax(g.y0 + (double)row * cell - py, 0.0);
