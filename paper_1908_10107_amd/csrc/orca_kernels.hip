@@ -514,38 +514,59 @@ __global__ __launch_bounds__(256) void k_fill_vel(const float *__restrict__ vel,
 // ------------------------------------------------------------------ neighbours
 
 // The running neighbour list of one lane: KMAX sorted 64-bit keys
-// (d2 bits << 32 | id + 1).  For K < KMAX the first KMAX - K slots hold the
-// key 0, below every real key, so the K nearest always sit in the last K
-// slots and the K-th is best[KMAX - 1] whatever K is.  Unfilled slots hold
-// ~0.  Offer key to the list.
+// (d2 bits + kKeyBias) << 32 | id + 1.  The bias lifts the top 12 bits of
+// every key to a positive normal double's exponent field (the float32 d2 bits
+// stay below the infinity pattern), and positive doubles order like their bit
+// patterns, so one v_min_f64 / v_max_f64 on the patterns compares two keys:
+// by d2, then by id.  For K < KMAX the first KMAX - K slots hold the key 0,
+// below every real key, so the K nearest always sit in the last K slots and
+// the K-th is best[KMAX - 1] whatever K is.  Unfilled slots hold the pattern
+// of +infinity.
+constexpr uint32_t kKeyBias = 0x00100000u;
+constexpr uint64_t kKeyEmpty = 0x7ff0000000000000ull;
+
+// Offer key to the sorted list.  Each slot takes the larger of its lower
+// neighbour and the smaller of itself and the key: the lower slots shift up
+// past the key, the key lands in the first slot above it, the rest stay.  A
+// key above the last slot changes nothing.  Each step is one v_min_f64 or
+// v_max_f64 on the slot in place, written out because fmin / fmax first quiet
+// every operand that the compiler cannot prove is not a signalling NaN (one
+// more instruction per slot); no key is a NaN pattern, and each result is one
+// operand's exact pattern.
+__device__ __forceinline__ void key_min_into(uint64_t &slot, uint64_t key)
+{
+    asm volatile("v_min_f64 %0, %1, %0" : "+v"(slot) : "v"(key));
+}
+__device__ __forceinline__ void key_max_into(uint64_t &slot, uint64_t lower)
+{
+    asm volatile("v_max_f64 %0, %1, %0" : "+v"(slot) : "v"(lower));
+}
 template <int KMAX>
 __device__ __forceinline__ void knn_offer(uint64_t (&best)[KMAX], uint64_t key)
 {
-    if (key >= best[KMAX - 1]) return;
 #pragma unroll
     for (int k = KMAX - 1; k > 0; --k) {
-        const bool shift = key < best[k - 1];
-        const bool here = key < best[k];
-        best[k] = shift ? best[k - 1] : (here ? key : best[k]);
+        key_min_into(best[k], key);
+        key_max_into(best[k], best[k - 1]);
     }
-    best[0] = key < best[0] ? key : best[0];
+    key_min_into(best[0], key);
 }
 
 // Offer the candidates [i, ie) of one row run (sorted indices) to the sorted
-// key list.  lim is the largest float32 bit pattern of d2 that can still
-// enter: strictly inside neighbor_dist and no farther than the list's K-th
-// entry (d2 >= 0, so the bit patterns order like the values; a NaN's pattern
-// exceeds every limit).  The agent itself (id myid) is skipped when it comes
-// up for insertion.
+// key list.  lim is the largest float32 bit pattern of d2, plus kKeyBias, that
+// can still enter: strictly inside neighbor_dist and no farther than the
+// list's K-th entry (d2 >= 0, so the bit patterns order like the values; a
+// NaN's pattern exceeds every limit).  The agent itself (id myid) is skipped
+// when it comes up for insertion.
 template <int KMAX>
 __device__ __forceinline__ void knn_run(uint64_t (&best)[KMAX], uint32_t &lim, uint32_t nd_lim,
                                         float mx, float my, uint32_t myid, int32_t i, int32_t ie,
                                         const float4 *__restrict__ sorted,
                                         const int32_t *__restrict__ sid)
 {
-    auto offer = [&](uint32_t hi, uint32_t id) __attribute__((always_inline)) {
+    auto offer = [&](uint32_t hb, uint32_t id) __attribute__((always_inline)) {
         if (id == myid) return;
-        knn_offer<KMAX>(best, ((uint64_t)hi << 32) | (id + 1u));
+        knn_offer<KMAX>(best, ((uint64_t)hb << 32) | (id + 1u));
         lim = min(nd_lim, (uint32_t)(best[KMAX - 1] >> 32));
     };
     // candidates two at a time: their positions and ids are loaded together,
@@ -561,14 +582,14 @@ __device__ __forceinline__ void knn_run(uint64_t (&best)[KMAX], uint32_t &lim, u
         for (int u = 0; u < kBatch; ++u) idb[u] = (uint32_t)sid[i + u];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const uint32_t hi = __float_as_uint(dist2_f32(mx, my, o[u].x, o[u].y));
-            if (hi <= lim) offer(hi, idb[u]);
+            const uint32_t hb = __float_as_uint(dist2_f32(mx, my, o[u].x, o[u].y)) + kKeyBias;
+            if (hb <= lim) offer(hb, idb[u]);
         }
     }
     for (; i < ie; ++i) {
         const float4 o = sorted[i];
-        const uint32_t hi = __float_as_uint(dist2_f32(mx, my, o.x, o.y));
-        if (hi <= lim) offer(hi, (uint32_t)sid[i]);
+        const uint32_t hb = __float_as_uint(dist2_f32(mx, my, o.x, o.y)) + kKeyBias;
+        if (hb <= lim) offer(hb, (uint32_t)sid[i]);
     }
 }
 
@@ -621,7 +642,7 @@ __device__ __forceinline__ void knn_rows(uint64_t (&best)[KMAX], uint32_t &lim, 
         const int32_t row = cy + dy;
         if (row < 0 || row >= g.ny) continue;
         // the chord's radius: nd, or the list's current limit after the inner cells
-        const double r = part != 1 ? fmin(nd, sqrt((double)__uint_as_float(lim))) : nd;
+        const double r = part != 1 ? fmin(nd, sqrt((double)__uint_as_float(lim - kKeyBias))) : nd;
         const double rx = r * (1.0 + 1e-6) + slack;
         double dyc = 0.0;  // distance from the agent to the row's band in y
         if (dy > 0) dyc = fmax(g.y0 + (double)row * cell - py, 0.0);
@@ -668,8 +689,8 @@ __device__ __forceinline__ int32_t knn_search(uint64_t (&best)[KMAX], float4 me,
     }
     const int32_t pad = KMAX - K;  // leading slots that hold the key 0
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) best[k] = k < pad ? 0ull : ~0ull;
-    const uint32_t nd_lim = __float_as_uint(nd2) - 1u;
+    for (int k = 0; k < KMAX; ++k) best[k] = k < pad ? 0ull : kKeyEmpty;
+    const uint32_t nd_lim = __float_as_uint(nd2) - 1u + kKeyBias;
     uint32_t lim = nd_lim;
     knn_rows<KMAX>(best, lim, nd_lim, me, (uint32_t)myid, g, ndf, sorted, sid, cell_start);
     return pad;
@@ -682,7 +703,7 @@ template <int KMAX>
 __device__ __forceinline__ int32_t knn_entry(const uint64_t (&best)[KMAX], int k, int32_t pad,
                                              int32_t myid, const int32_t *__restrict__ inv)
 {
-    if (k < pad || best[k] == ~0ull) return -1;
+    if (k < pad || best[k] == kKeyEmpty) return -1;
     const uint32_t jid = (uint32_t)(best[k] & 0xffffffffu) - 1u;
     const uint32_t later = (uint32_t)myid < jid ? 0u : 0x80000000u;
     return (int32_t)((uint32_t)inv[jid] | later);
@@ -721,27 +742,19 @@ __attribute__((amdgpu_waves_per_eu(KMAX <= 16 ? ORCA_KNN_WAVES : 1))) void k_knn
     const GridDev g = grid[sc];
     const int32_t K = sp[sc].k;
     const float nd2 = sp[sc].nd2;
-    // d2 < nd2 as bit patterns: at most the pattern just below nd2's (an nd2
-    // that underflowed to zero admits nobody)
     if (K == 0 || !(nd2 > 0.0f)) {
         ncount[s] = 0;
         return;
     }
-    const uint32_t nd_lim = __float_as_uint(nd2) - 1u;
-    uint32_t lim = nd_lim;
     uint64_t best[KMAX];
-    const int32_t pad = KMAX - K;  // leading slots that hold the key 0
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) best[k] = k < pad ? 0ull : ~0ull;
-    knn_rows<KMAX>(best, lim, nd_lim, me, (uint32_t)myid, g, sp[sc].nd, sorted, sid, cell_start);
+    const int32_t pad = knn_search<KMAX>(best, me, myid, g, K, nd2, sp[sc].nd, sorted, sid,
+                                         cell_start);
     int32_t cnt = 0;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        if (k >= pad && best[k] != ~0ull) {
-            const uint32_t jid = (uint32_t)(best[k] & 0xffffffffu) - 1u;
-            // bit 31: this agent does not come first of the pair (ids order it)
-            const uint32_t later = (uint32_t)myid < jid ? 0u : 0x80000000u;
-            nbr[(int64_t)(k - pad) * ld + s] = (int32_t)((uint32_t)inv[jid] | later);
+        const int32_t e = knn_entry<KMAX>(best, k, pad, myid, inv);
+        if (e != -1) {
+            nbr[(int64_t)(k - pad) * ld + s] = e;
             cnt = k - pad + 1;
         }
     }
