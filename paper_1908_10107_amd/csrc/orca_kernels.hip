@@ -252,14 +252,33 @@ __global__ __launch_bounds__(256) void k_grid(int32_t n_scenes, const int32_t *_
         if (total <= (unsigned long long)max_cells) break;
         f *= sqrt((double)total / (double)max_cells) * 1.05;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t base = 0;
-        for (int32_t s = 0; s < n_scenes; ++s) {
-            grid[s].base = (int32_t)base;
-            base += (uint32_t)grid[s].nx * (uint32_t)grid[s].ny;
+    // first cell of each scene: an exclusive scan of the scenes' cell counts,
+    // a block's width of scenes at a time (each thread reads back the grids it
+    // wrote itself); the total fits 32 bits, being at most max_cells
+    __shared__ uint32_t wsum[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+    uint32_t carry = 0;
+    for (int32_t s0 = 0; s0 < n_scenes; s0 += blockDim.x) {
+        const int32_t s = s0 + threadIdx.x;
+        const uint32_t c = s < n_scenes ? (uint32_t)grid[s].nx * (uint32_t)grid[s].ny : 0u;
+        uint32_t inc = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
         }
-        counters->total_cells = base + (life ? 1u : 0u);
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        uint32_t wprefix = 0, total = 0;
+        for (int w = 0; w < waves; ++w) {
+            wprefix += w < wave ? wsum[w] : 0u;
+            total += wsum[w];
+        }
+        if (s < n_scenes) grid[s].base = (int32_t)(carry + wprefix + inc - c);
+        carry += total;
+        __syncthreads();  // wsum is reused
+    }
+    if (threadIdx.x == 0) {
+        counters->total_cells = carry + (life ? 1u : 0u);
         counters->n_fallback = 0;
     }
     if (threadIdx.x < kXcds) counters->tiles[threadIdx.x] = 0u;
