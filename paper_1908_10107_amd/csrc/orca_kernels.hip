@@ -842,12 +842,13 @@ struct EntriesInRegs {
 };
 
 // Load the m neighbours of agent id (state me) and build their half-planes
-// into `rows`.  The neighbour loads are issued G at a time before those
-// half-planes are built, so one memory latency covers each group: two with
-// the rows in registers, which keeps the LP kernels within the registers of
-// three waves per SIMD (the other waves then cover the latency), eight with
-// the rows in LDS.  Neighbour ids are fetched only when they are written out
-// (the pair order comes with the entry).
+// into `rows`.  The neighbour loads are issued G at a time, so one memory
+// latency covers each group: two with the rows in registers, which keeps the
+// LP kernels within the registers of three waves per SIMD, each group's
+// gathers issued while the group before it is built (k_lp at 1M agents,
+// K = 16: 289 to 283 us); eight with the rows in LDS, each group loaded
+// before it is built.  Neighbour ids are fetched only when they are written
+// out (the pair order comes with the entry).
 template <int KMAX, class Rows, class Src>
 __device__ __forceinline__ void build_constraints(Rows &rows, const Src &src, int m, int32_t id,
                                                   float4 me, const SceneDev &p,
@@ -862,6 +863,53 @@ __device__ __forceinline__ void build_constraints(Rows &rows, const Src &src, in
     const double tau = (double)p.tau, dt = (double)p.dt;
     const double inv_tau = 1.0 / tau, inv_dt = 1.0 / dt;  // shared by every row
     const double vix = (double)me.z, viy = (double)me.w;
+    if constexpr (KMAX <= kLpRegRows) {
+        // every entry first (independent, coalesced loads; the rows are not
+        // yet live, so their registers are free), then the neighbours G at a
+        // time with the next group's gathers issued before this group's
+        // half-planes are built
+        int32_t e[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) e[k] = k < m ? src(k) : 0;
+        auto gather = [&](int k) __attribute__((always_inline)) -> float4 {
+            return k < m ? sorted[e[k] & 0x7fffffff] : make_float4(0.f, 0.f, 0.f, 0.f);
+        };
+        float4 cur[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) cur[u] = gather(u);
+#pragma unroll
+        for (int k0 = 0; k0 < KMAX; k0 += G) {
+            float4 nxt[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+                nxt[u] = k0 + G + u < KMAX ? gather(k0 + G + u) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int k = k0 + u;
+                if (k >= KMAX) continue;
+                const float rj = ag.radius && k < m ? ag.srad[e[k] & 0x7fffffff] : p.radius;
+                double2 nk = make_double2(0.0, 0.0);
+                double bk = 0.0;
+                if (k < m) {
+                    const double Px = (double)cur[u].x - (double)me.x;
+                    const double Py = (double)cur[u].y - (double)me.y;
+                    const double Vx = vix - (double)cur[u].z, Vy = viy - (double)cur[u].w;
+                    double ux, uy, nx, ny;
+                    obstacle_exit(Px, Py, Vx, Vy, ri + (double)rj, tau, dt, inv_tau, inv_dt,
+                                  e[k] >= 0, ux, uy, nx, ny);
+                    const double qx = vix + 0.5 * ux, qy = viy + 0.5 * uy;
+                    nk = make_double2(nx, ny);
+                    bk = nx * qx + ny * qy;
+                }
+                rows.set(k, nk, bk);
+                if (nbr_out && k < krow)
+                    nbr_out[(int64_t)id * krow + k] = k < m ? sid[e[k] & 0x7fffffff] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) cur[u] = nxt[u];
+        }
+        return;
+    }
 #pragma unroll
     for (int k0 = 0; k0 < KMAX; k0 += G) {
         int32_t e[G];
