@@ -34,7 +34,9 @@ __device__ __forceinline__ double wave_sum_f64(double v)
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_backward(
     BackArgs a)
 {
-    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;  // sorted index
+    // sorted index, neighbouring tiles on one XCD (the atomics on shared
+    // neighbours come from one XCD's waves)
+    const int32_t s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int32_t n = a.n;
     const bool live = s < n;
     int32_t sc = 0;

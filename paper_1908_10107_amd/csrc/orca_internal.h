@@ -20,6 +20,17 @@ constexpr int kMaxCellsPerNd = 4;                   // .. 4, per scene (k_grid)
 constexpr int kFbSortChunk = 4096;                  // fallback slots sorted together
 constexpr int kFbSortBlock = 1024;                  // threads per fallback-sort block (4 slots each)
 
+// Tile of block b of nb.  Workgroups are handed to the 8 XCDs round robin
+// (block b to XCD b mod 8), and each XCD has its own L2; this mapping gives
+// each XCD one contiguous range of tiles, so agents that share neighbours (cell
+// order) meet in the same L2.  A bijection of [0, nb) for any nb.
+constexpr int32_t kXcds = 8;
+__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t nb)
+{
+    const int32_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds, i = b / kXcds;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // Per-scene parameters as the kernels read them.
 struct SceneDev {
     float radius, vmax, nd, tau, dt, pref_speed;

@@ -67,21 +67,6 @@ __device__ __forceinline__ uint32_t wave_reduce_sum_u32(uint32_t v)
     return v;
 }
 
-// Tile of block b of nb.  Workgroups are handed to the 8 XCDs round robin
-// (block b to XCD b mod 8), and each XCD has its own L2; this mapping gives
-// each XCD one contiguous range of tiles, so agents that share neighbours (cell
-// order) meet in the same L2.  A bijection of [0, nb) for any nb.
-#ifndef ORCA_XCD_SWIZZLE
-#define ORCA_XCD_SWIZZLE 1
-#endif
-constexpr int32_t kXcds = 8;
-__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t nb)
-{
-    if (!ORCA_XCD_SWIZZLE) return b;
-    const int32_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds, i = b / kXcds;
-    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
 // Squared distance in float32 with every operation rounded on its own (no
 // fused multiply-add): the neighbour set is decided by this value.
 __device__ __forceinline__ float dist2_f32(float xi, float yi, float xj, float yj)
