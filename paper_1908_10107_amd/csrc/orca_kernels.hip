@@ -68,7 +68,11 @@ __device__ __forceinline__ uint32_t wave_reduce_sum_u32(uint32_t v)
 }
 
 // Squared distance in float32 with every operation rounded on its own (no
-// fused multiply-add): the neighbour set is decided by this value.
+// fused multiply-add): the neighbour set is decided by this value.  The
+// squares are added as absolute values (input modifiers, no instruction):
+// the same value for any finite input, and a NaN from non-finite positions
+// comes out with its sign bit clear, so its bit pattern exceeds every
+// distance limit.
 __device__ __forceinline__ float dist2_f32(float xi, float yi, float xj, float yj)
 {
 #pragma clang fp contract(off)
@@ -76,7 +80,7 @@ __device__ __forceinline__ float dist2_f32(float xi, float yi, float xj, float y
     const float dy = yj - yi;
     const float sx = dx * dx;
     const float sy = dy * dy;
-    return sx + sy;
+    return fabsf(sx) + fabsf(sy);
 }
 
 // ------------------------------------------------------------------ grid
@@ -656,6 +660,11 @@ __device__ __forceinline__ void knn_rows(uint64_t (&best)[KMAX], uint32_t &lim, 
         int32_t c0 = max((int32_t)fmax(floor((px - hw - g.x0) / cell), -1.0), max(cx - reach, 0));
         int32_t c1 = min((int32_t)fmin(floor((px + hw - g.x0) / cell), (double)g.nx),
                          min(cx + reach, g.nx - 1));
+        // the agent's own column always: an agent inside the grid's extent
+        // has it in its chord anyway, one outside (a scene that is one cell
+        // at origin 0 because its box is not finite) still reads its cell
+        c0 = min(c0, cx);
+        c1 = max(c1, cx);
         if (part == 1) {
             c0 = max(c0, cx - 1);
             c1 = min(c1, cx + 1);

@@ -222,6 +222,39 @@ def test_multi_scene_with_empty_scenes():
     compare(b, g, o, label="multi-scene")
 
 
+def test_nan_position_is_nobodys_neighbour():
+    """An agent at a NaN position whose float32 pattern has the sign bit and
+    every payload bit set: its squared distance to anyone is NaN, which must
+    fail the distance test however the neighbour list encodes distances (a
+    key built from the raw pattern would wrap around to the nearest).  The
+    scene then has a non-finite bounding box, so the whole scene is one cell."""
+    say("case NaN position")
+    w = scenes.tiny_random(64, 12.0, seed=5, max_neighbors=8)
+    w.pos[:, 17] = np.frombuffer(np.uint32(0xFFFFFFFF).tobytes(), np.float32)[0]
+    g = gpu_velocities(w, use_goals=False)
+    o = oracle.velocities(w.pos, w.vel, w.pref_vel, w.offsets, w.params, neighbor_mode=0)
+    assert not np.any(o["nbr"] == 17)
+    compare(w, g, o, label="NaN position")
+
+
+def test_many_small_scenes():
+    """More scenes than one block of the grid kernel takes at a time (256),
+    with a partial last block and empty scenes on both sides of the block
+    boundary: every scene's cells start where the scan of the cell counts
+    puts them."""
+    say("case 300 small scenes")
+    b = scenes.batched(n_scenes=298, n_min=8, n_max=64, seed=21)
+    offs = list(b.offsets)
+    offs = offs[:256] + [offs[255]] + offs[256:258] + [offs[257]] + offs[258:]
+    b.offsets = np.array(offs, np.int64)
+    b.params = b.params[:255] + [b.params[255]] + b.params[255:257] + [b.params[256]] + b.params[257:]
+    assert b.n_scenes == 300 and b.n_scenes == len(b.params)
+    g = gpu_velocities(b, use_goals=True)
+    o = oracle.velocities(b.pos, b.vel, b.pref_vel, b.offsets, b.params, goals=b.goals,
+                          neighbor_mode=0)
+    compare(b, g, o, label="300 scenes")
+
+
 def test_empty_workload():
     torch = _torch()
     from paper_1908_10107_amd import orca
