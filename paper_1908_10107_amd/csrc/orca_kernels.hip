@@ -634,49 +634,64 @@ __device__ __forceinline__ void knn_rows(uint64_t (&best)[KMAX], uint32_t &lim, 
     const double px = (double)me.x, py = (double)me.y;
     const double slack = 1e-9 * (1.0 + fabs(px) + fabs(py));
     // segments (one knn_run call site keeps the registers of one row loop):
-    // 0-2 the inner three columns of rows 0, -1, +1 over the full chord;
-    // 3-8 the columns left and right of them in the same rows, and 9-14 rows
-    // -2, +2, -3, +3, -4, +4 (those within reach), over chords cut to the
-    // list's current limit.
+    // 0-2 the inner three columns of rows 0, -1, +1; 3-8 the columns left and
+    // right of them in the same rows, and 9-14 rows -2, +2, -3, +3, -4, +4
+    // (those within reach), over chords cut to the list's current limit.
     constexpr int32_t kSegs = 9 + 2 * (kMaxCellsPerNd - 1);
+    // The inner segments read columns cx - 1 .. cx + 1 whatever the chord:
+    // at least the columns the chord would give (every candidate is tested
+    // anyway, and the order of the offers does not change the list), and
+    // with cells no wider than about nd / 2 exactly those.
+    // outer chords: columns from the chord's ends times 1 / cell (a quotient
+    // off by an ulp or two only where the widened chord ends within that of
+    // a cell edge, which the disc itself never reaches)
+    const double inv_cell = 1.0 / cell;
 #pragma unroll 1
     for (int32_t q = 0; q < kSegs; ++q) {
-        // row code (dy = 0, -1, +1, -2, +2, ...) and part: 1 inner, 2 left,
-        // 3 right, 0 the whole chord
-        const int32_t qr = q < 3 ? q : (q < 9 ? (q - 3) >> 1 : q - 6);
-        const int32_t part = q < 3 ? 1 : (q < 9 ? 2 + ((q - 3) & 1) : 0);
-        const int32_t dy = (qr & 1) ? -((qr + 1) >> 1) : (qr >> 1);
-        if (dy > reach || -dy > reach) continue;
-        const int32_t row = cy + dy;
-        if (row < 0 || row >= g.ny) continue;
-        // the chord's radius: nd, or the list's current limit after the inner cells
-        const double r = part != 1 ? fmin(nd, sqrt((double)__uint_as_float(lim - kKeyBias))) : nd;
-        const double rx = r * (1.0 + 1e-6) + slack;
-        double dyc = 0.0;  // distance from the agent to the row's band in y
-        if (dy > 0) dyc = fmax(g.y0 + (double)row * cell - py, 0.0);
-        if (dy < 0) dyc = fmax(py - (g.y0 + (double)(row + 1) * cell), 0.0);
-        if (dyc >= rx) continue;
-        const double hw = sqrt(rx * rx - dyc * dyc);
-        int32_t c0 = max((int32_t)fmax(floor((px - hw - g.x0) / cell), -1.0), max(cx - reach, 0));
-        int32_t c1 = min((int32_t)fmin(floor((px + hw - g.x0) / cell), (double)g.nx),
-                         min(cx + reach, g.nx - 1));
-        // the agent's own column always: an agent inside the grid's extent
-        // has it in its chord anyway, one outside (a scene that is one cell
-        // at origin 0 because its box is not finite) still reads its cell
-        c0 = min(c0, cx);
-        c1 = max(c1, cx);
-        if (part == 1) {
-            c0 = max(c0, cx - 1);
-            c1 = min(c1, cx + 1);
-        } else if (part == 2) {
-            c1 = min(c1, cx - 2);
-        } else if (part == 3) {
-            c0 = max(c0, cx + 2);
+        int32_t i, ie;
+        if (q < 3) {
+            const int32_t row = cy + (q == 0 ? 0 : (q == 1 ? -1 : 1));
+            if (row < 0 || row >= g.ny) continue;
+            const int32_t rb = g.base + row * g.nx;
+            i = cell_start[rb + max(cx - 1, 0)];
+            ie = cell_start[rb + min(cx + 1, g.nx - 1) + 1];
+        } else {
+            // row code (dy = -1, +1, -2, +2, ...) and part: 2 left, 3 right,
+            // 0 the whole chord
+            const int32_t qr = q < 9 ? (q - 3) >> 1 : q - 6;
+            const int32_t part = q < 9 ? 2 + ((q - 3) & 1) : 0;
+            const int32_t dy = (qr & 1) ? -((qr + 1) >> 1) : (qr >> 1);
+            if (dy > reach || -dy > reach) continue;
+            const int32_t row = cy + dy;
+            if (row < 0 || row >= g.ny) continue;
+            // the chord's radius: the list's current limit, at most nd
+            const double r = fmin(nd, sqrt((double)__uint_as_float(lim - kKeyBias)));
+            const double rx = r * (1.0 + 1e-6) + slack;
+            double dyc = 0.0;  // distance from the agent to the row's band in y
+            if (dy > 0) dyc = fmax(g.y0 + (double)row * cell - py, 0.0);
+            if (dy < 0) dyc = fmax(py - (g.y0 + (double)(row + 1) * cell), 0.0);
+            if (dyc >= rx) continue;
+            const double hw = sqrt(rx * rx - dyc * dyc);
+            int32_t c0 = max((int32_t)fmax(floor((px - hw - g.x0) * inv_cell), -1.0),
+                             max(cx - reach, 0));
+            int32_t c1 = min((int32_t)fmin(floor((px + hw - g.x0) * inv_cell), (double)g.nx),
+                             min(cx + reach, g.nx - 1));
+            // the agent's own column always: an agent inside the grid's extent
+            // has it in its chord anyway, one outside (a scene that is one cell
+            // at origin 0 because its box is not finite) still reads its cell
+            c0 = min(c0, cx);
+            c1 = max(c1, cx);
+            if (part == 2) {
+                c1 = min(c1, cx - 2);
+            } else if (part == 3) {
+                c0 = max(c0, cx + 2);
+            }
+            if (c0 > c1) continue;
+            const int32_t rb = g.base + row * g.nx;
+            i = cell_start[rb + c0];
+            ie = cell_start[rb + c1 + 1];
         }
-        if (c0 > c1) continue;
-        const int32_t rb = g.base + row * g.nx;
-        knn_run<KMAX>(best, lim, nd_lim, me.x, me.y, myid, cell_start[rb + c0],
-                      cell_start[rb + c1 + 1], sorted, sid);
+        knn_run<KMAX>(best, lim, nd_lim, me.x, me.y, myid, i, ie, sorted, sid);
     }
 }
 
