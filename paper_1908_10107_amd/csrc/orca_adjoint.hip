@@ -31,16 +31,27 @@ __device__ __forceinline__ double wave_sum_f64(double v)
 // Held to the registers of three waves per SIMD (a few bytes of spill): the
 // kernel waits on its neighbour gathers and float64 chains, which a third
 // wave covers better than the unconstrained two.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_backward(
+constexpr int kBackBlock = 256;  // threads (sorted indices) per k_backward block
+
+__global__ __launch_bounds__(kBackBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_backward(
     BackArgs a)
 {
     // sorted index, neighbouring tiles on one XCD (the atomics on shared
     // neighbours come from one XCD's waves)
-    const int32_t s = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int32_t b0 = xcd_tile(blockIdx.x, gridDim.x) * kBackBlock;
+    const int32_t s = b0 + threadIdx.x;
     const int32_t n = a.n;
     const bool live = s < n;
+    // the shares of neighbours within this block's own sorted range: summed
+    // in LDS and stored with each agent's own share, so only neighbours
+    // outside the block take global atomics
+    __shared__ double lacc[4][kBackBlock];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lacc[c][threadIdx.x] = 0.0;
+    __syncthreads();
     int32_t sc = 0;
     double gvmax = 0.0, gtau = 0.0;
+    double gvix = 0.0, gviy = 0.0, gxi = 0.0, gyi = 0.0;
     if (live) {
         const int32_t i = a.sid[s];
         // a recorded step's scenes keep their index ranges in cell order
@@ -101,8 +112,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         double gvhx = 0.0, gvhy = 0.0;
         choice_vjp(rows, tc, vmax, vhx, vhy, gx, gy, sg, gvhx, gvhy, gvmax);
         // agent i's own share is summed over its slots first: four atomics
-        // per neighbour and four for i
-        double gvix = 0.0, gviy = 0.0, gxi = 0.0, gyi = 0.0;
+        // per neighbour outside the block, none for i
 #pragma unroll
         for (int q = 0; q < kSlots; ++q) {
             if (js[q] < 0) continue;
@@ -111,21 +121,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     sg.gb[q], gPx, gPy, gVx, gVy, gtau, gvix, gviy);
             const int32_t j = js[q];
             // P = x_j - x_i, V = v_i - v_j
-            atomicAdd(&a.acc[j], gPx);
-            atomicAdd(&a.acc[n + j], gPy);
-            atomicAdd(&a.acc[2 * n + j], -gVx);
-            atomicAdd(&a.acc[3 * n + j], -gVy);
+            const uint32_t lj = (uint32_t)(j - b0);
+            if (lj < (uint32_t)kBackBlock) {
+                atomicAdd(&lacc[0][lj], gPx);
+                atomicAdd(&lacc[1][lj], gPy);
+                atomicAdd(&lacc[2][lj], -gVx);
+                atomicAdd(&lacc[3][lj], -gVy);
+            } else {
+                atomicAdd(&a.acc[j], gPx);
+                atomicAdd(&a.acc[n + j], gPy);
+                atomicAdd(&a.acc[2 * n + j], -gVx);
+                atomicAdd(&a.acc[3 * n + j], -gVy);
+            }
             gxi -= gPx;
             gyi -= gPy;
             gvix += gVx;
             gviy += gVy;
         }
-        // the agent's own share: each sorted index is written by its own
-        // lane only, so plain stores beside the neighbours' atomics
-        a.own[s] = gxi;
-        a.own[n + s] = gyi;
-        a.own[2 * n + s] = gvix;
-        a.own[3 * n + s] = gviy;
         if (a.g_pref2) {
             float2 gp = a.g_pref2[i];
             gp.x += (float)gvhx;
@@ -136,6 +148,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             a.g_pref[n + i] += (float)gvhy;
         }
         if (a.max_speed) gvmax = 0.0;  // the agent's own max speed is a constant here
+    }
+    __syncthreads();
+    if (live) {
+        // the agent's own share and the block's shares for it: each sorted
+        // index is written by its own lane only, so plain stores beside the
+        // other blocks' atomics
+        a.own[s] = gxi + lacc[0][threadIdx.x];
+        a.own[n + s] = gyi + lacc[1][threadIdx.x];
+        a.own[2 * n + s] = gvix + lacc[2][threadIdx.x];
+        a.own[3 * n + s] = gviy + lacc[3][threadIdx.x];
     }
     // per-scene parameters: one atomic per wave when the wave is one scene
     const int32_t sc0 = __shfl(sc, 0, 64);
@@ -232,7 +254,8 @@ hipError_t launch_backward_post(const float2 *g_pref2, float *g_pref, int32_t n,
 hipError_t launch_backward(const BackArgs &a, hipStream_t st)
 {
     if (a.n > 0)
-        hipLaunchKernelGGL(k_backward, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_backward, dim3((a.n + kBackBlock - 1) / kBackBlock), dim3(kBackBlock),
+                           0, st, a);
     const int32_t m = a.n > a.n_scenes ? a.n : a.n_scenes;
     if (m > 0) hipLaunchKernelGGL(k_backward_finish, dim3((m + 255) / 256), dim3(256), 0, st, a);
     return hipGetLastError();
