@@ -10,9 +10,11 @@
 //   to vhat_i and to v_max, then through each half-plane to its relative
 //   position P = x_j - x_i, relative velocity V = v_i - v_j, v_i (through
 //   v_i + u/2) and tau;
-//   scatter P and V gradients to neighbours j with float64 atomics into
-//   accumulators indexed by the step's sorted index, and store agent i's own
-//   share (summed over its rows) beside them.
+//   scatter P and V gradients to neighbours j: within the block's own range
+//   of sorted indices into LDS, outside it with float64 atomics into
+//   accumulators indexed by the step's sorted index; then store agent i's
+//   own share (summed over its rows) plus the block's shares for it beside
+//   them.
 // k_backward_finish then writes dL/dx = dL/dx' + (scattered part), dL/dv
 // (scattered part) by agent id, adds the per-scene v_max and tau gradients,
 // and clears the float64 accumulators for the next use.
