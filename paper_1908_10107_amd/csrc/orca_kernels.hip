@@ -766,7 +766,10 @@ __attribute__((amdgpu_waves_per_eu(KMAX <= 16 ? ORCA_KNN_WAVES : 1))) void k_knn
     if (s >= n_present) return;
     const float4 me = sorted[s];
     const int32_t myid = sid[s];
-    const int32_t sc = agent_scene[myid];
+    // without spawning each scene holds the same index range in cell order
+    // as in agent order (its cells come in scene order), so the scene is
+    // read by sorted index, not gathered by id
+    const int32_t sc = agent_scene[life ? myid : s];
     const GridDev g = grid[sc];
     const int32_t K = sp[sc].k;
     const float nd2 = sp[sc].nd2;
@@ -1173,7 +1176,7 @@ __attribute__((amdgpu_waves_per_eu(KMAX <= kLpRegRows ? 3 : 1))) void k_lp(
     if (s < n_present) {
         const float4 me = sorted[s];
         const int32_t id = sid[s];
-        const SceneDev p = sp[agent_scene[id]];
+        const SceneDev p = sp[agent_scene[LIFE ? id : s]];  // as in k_knn
         need_fb = lp_agent<KMAX, MODE>(rows, it, EntriesInMemory{nbr, ld, s}, ncount[s], s, me,
                                        id, p, out, n, sorted, sid);
     }
@@ -1228,7 +1231,7 @@ __attribute__((amdgpu_waves_per_eu(KMAX <= kLpRegRows ? 3 : 1))) void k_velocity
                 if (s < n) {
                     const float4 me = sorted[s];
                     const int32_t id = sid[s];
-                    const int32_t sc = agent_scene[id];
+                    const int32_t sc = agent_scene[s];  // as in k_knn
                     const SceneDev p = sp[sc];
                     int32_t e[KMAX];
                     int m = 0;
