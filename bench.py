@@ -246,12 +246,16 @@ def cpu_baseline(w, min_seconds: float, evolved=None):
 
 def full_length_forms(launch):
     """Each workload over its whole length from t = 0 in one call (one
-    orca_step of all steps, or graph replays for the 512 scenes)."""
+    orca_step of all steps, or graph replays), the two smaller ones both
+    ways: at their sizes a step's kernels are short enough for the host's
+    launches to show."""
     import torch
     from paper_1908_10107_amd import orca, scenes
     out = {}
     for name, make, graph in (("uniform_rsa_1024x100", scenes.uniform_rsa, False),
+                              ("uniform_rsa_1024x100_graph", scenes.uniform_rsa, True),
                               ("ring_65536x2000", scenes.ring, False),
+                              ("ring_65536x2000_graph", scenes.ring, True),
                               ("dense_1M_x500", scenes.dense_uniform, False),
                               ("batched_512x300", scenes.batched, True)):
         w = make()
