@@ -1136,13 +1136,13 @@ __device__ __forceinline__ void append_fallback(bool need_fb, const FallbackItem
 
 // One lane per agent in cell order, half-planes in registers (LDS above 16
 // rows).  With the rows in registers the kernel is held to the registers of
-// three waves per SIMD: it is bound by the latency of its float64 chains and
-// gathers, which a third wave covers better than the unconstrained two (a few
-// bytes of spill).  Feasible agents finish here; the others go to the
-// fallback list.
+// three waves per SIMD, four up to 10 rows: it is bound by the latency of its
+// float64 chains and gathers, which another wave covers better than the
+// unconstrained count (a few bytes of spill).  Feasible agents finish here;
+// the others go to the fallback list.
 template <int KMAX, int MODE>
 __global__ __launch_bounds__(kLpBlock)
-__attribute__((amdgpu_waves_per_eu(KMAX <= kLpRegRows ? 3 : 1))) void k_lp(
+__attribute__((amdgpu_waves_per_eu(KMAX <= 10 ? 4 : (KMAX <= kLpRegRows ? 3 : 1)))) void k_lp(
     const float4 *__restrict__ sorted, const int32_t *__restrict__ sid,
     const int32_t *__restrict__ agent_scene, const SceneDev *__restrict__ sp, int32_t n,
     const int32_t *__restrict__ nbr, int32_t ld, const int32_t *__restrict__ ncount, OutArgs out,
