@@ -740,14 +740,14 @@ __device__ __forceinline__ int32_t knn_entry(const uint64_t (&best)[KMAX], int k
 // K nearest of each agent (sorted order s), as knn_search finds them (the
 // candidates from knn_rows).  Writes nbr[k * ld + s] (entries as knn_entry
 // gives them) and ncount[s].  Held to the registers of six waves per SIMD up
-// to K = 16 (a few bytes of spill at K = 16): the search waits on its
-// candidate gathers, which the sixth wave covers.
+// to K = 16 and eight up to K = 10 (a few bytes of spill): the search waits on
+// its candidate gathers, which the extra waves cover.
 #ifndef ORCA_KNN_WAVES
 #define ORCA_KNN_WAVES 6
 #endif
 template <int KMAX>
 __global__ __launch_bounds__(512)
-__attribute__((amdgpu_waves_per_eu(KMAX <= 16 ? ORCA_KNN_WAVES : 1))) void k_knn(const float4 *__restrict__ sorted,
+__attribute__((amdgpu_waves_per_eu(KMAX <= 10 ? 8 : (KMAX <= 16 ? ORCA_KNN_WAVES : 1)))) void k_knn(const float4 *__restrict__ sorted,
                                              const int32_t *__restrict__ sid,
                                              const int32_t *__restrict__ inv,
                                              const int32_t *__restrict__ cell_start,
